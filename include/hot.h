@@ -1,0 +1,189 @@
+/*
+ * hot.h -- C ABI of the MI355X hologram solver for holographic optical tweezers.
+ *
+ * Method: S. Bianchi and R. Di Leonardo, "Real-time optical micro-manipulation
+ * using optimized holograms generated on the GPU" (arXiv:0907.4027).
+ *   Eq. 1  V_m   = (1/N) sum_j exp(i (phi_j - Delta_j^m))          field at trap m
+ *   Eq. 2  Delta = z_m pi/(lambda f^2) (x_j^2 + y_j^2) + 2 pi/(lambda f) (x_j x_m + y_j y_m)
+ *   Eq. 3  phi_j = arg sum_m w_m exp(i (Delta_j^m + theta_m))       (w_m = 1: random superposition)
+ *   Section 3  e = sum_m |V_m|^2,  u = 1 - (max I - min I)/(max I + min I),  I_m = |V_m|^2
+ *   Section 3 / Fig. 2  GSW: w_m <- w_m <|V|>/|V_m|, theta_m <- arg V_m, repeat.
+ *
+ * Conventions shared by every entry point
+ *   Units      SI metres for pitch, wavelength, focal length and trap positions;
+ *              phases in radians.
+ *   Pixels     phase masks are row-major float arrays [ny][nx]; pixel j = r*nx + c
+ *              sits at x = (c - (nx-1)/2) * pitch, y = (r - (ny-1)/2) * pitch
+ *              (origin on the optical axis, every pixel counts, x along columns).
+ *   Output     phases in [0, 2 pi] (float rounding can return 2 pi itself);
+ *              V as interleaved (re, im) float pairs.
+ *   Precision  FP32 on the device; per-trap coefficients are formed in FP64 on
+ *              the host and rounded once.
+ *   Ownership  the caller owns every buffer passed in and out.  "device" pointers
+ *              are device memory on the context's GPU (e.g. torch data_ptr());
+ *              "host" pointers are ordinary CPU memory.  The library allocates
+ *              only inside the context and never frees caller memory.
+ *   Ordering   all device work is enqueued on the context's stream.  A call that
+ *              is given a host `stats` pointer synchronises that stream before it
+ *              returns; otherwise it returns as soon as the work is enqueued.
+ *   Errors     every int-returning call returns HOT_OK (0) or a negative code;
+ *              hot_last_error() then describes the failure (thread-local).  All
+ *              argument checks run on the host before any device work, so on an
+ *              error no output has been touched.  HOT_EDEGENERATE (every |V_m| = 0
+ *              during GSW/GS) is detected on the device and reported by the call
+ *              that synchronises (a call with `stats`, or hot_sync()).
+ *   Threads    a context may be used by one host thread at a time; calls that
+ *              overlap on one context race.
+ */
+#ifndef HOT_H
+#define HOT_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define HOT_ABI_VERSION 1
+#define HOT_MAX_TRAPS 2048  /* per hologram */
+#define HOT_MAX_SIDE 4096   /* nx, ny */
+#define HOT_MAX_BATCH 4096  /* holograms per batched call */
+
+typedef struct hot_ctx hot_ctx;
+
+/* SLM pixel grid and optics (Section 3, Fig. 1: SLM in the back focal plane). */
+typedef struct hot_slm {
+  int32_t nx, ny;     /* columns (x) and rows (y), 1..HOT_MAX_SIDE */
+  double pitch;       /* pixel pitch [m], > 0 */
+  double wavelength;  /* lambda [m], > 0 */
+  double focal;       /* effective focal length f [m], > 0 */
+} hot_slm;
+
+/* Per-iteration figures of merit (Section 3): efficiency e, uniformity u, and
+ * sigma = std(I)/mean(I) with the population standard deviation. */
+typedef struct hot_stats {
+  float efficiency, uniformity, sigma;
+} hot_stats;
+
+enum hot_status {
+  HOT_OK = 0,
+  HOT_EINVAL = -1,      /* bad argument (null pointer, size or value out of range, non-finite) */
+  HOT_ENOMEM = -2,      /* device or pinned-host allocation failed */
+  HOT_EDEVICE = -3,     /* no usable GPU, or a HIP runtime call failed */
+  HOT_EDEGENERATE = -4  /* GSW/GS met <|V|> = 0: the phase mask sends no light to any trap */
+};
+
+/* How the propagation phase Delta is obtained inside the two passes. */
+enum hot_variant {
+  HOT_ONTHEFLY = 0, /* Delta recomputed per (pixel, trap) with FP32 sin/cos (default) */
+  HOT_STORED = 1    /* exp(i Delta) precomputed once as a complex64 [M][N] matrix, then two GEMV-shaped passes */
+};
+
+/* ---- context ------------------------------------------------------------------------ */
+
+/* Create a context on HIP device `device`.  `stream` is the hipStream_t to enqueue on
+ * (e.g. torch.cuda.current_stream().cuda_stream); NULL means the device's default
+ * (null) stream, which is also torch's default stream.  Returns HOT_EDEVICE when no
+ * GPU is present. */
+int hot_create(hot_ctx** out, int device, void* stream);
+int hot_destroy(hot_ctx* ctx);
+/* Switch the stream later calls enqueue on (NULL: the default stream). */
+int hot_set_stream(hot_ctx* ctx, void* stream);
+/* Select HOT_ONTHEFLY or HOT_STORED for later calls (hot_rs, hot_gs, hot_gsw). */
+int hot_set_variant(hot_ctx* ctx, int variant);
+/* Launch-shape knobs (used by the autotuner; 0 restores the built-in choice).  They
+ * change how work is tiled, never what is computed beyond FP32 summation order. */
+enum hot_tuning_key {
+  HOT_TUNE_PIXELS_PER_LANE = 1, /* pixel pass: pixels per lane, 1, 2 or 4 */
+  HOT_TUNE_TRAPS_PER_LANE = 2,  /* trap pass: traps each lane accumulates, 1..8 */
+  HOT_TUNE_SEGMENT = 3,         /* trap pass: pixels of a row per block, 64..1024 */
+  HOT_TUNE_SLICES = 4           /* trap pass: at most this many pixel slices per wave, 1..16 */
+};
+int hot_set_tuning(hot_ctx* ctx, int key, int value);
+
+/* Wait for the context's stream; returns HOT_EDEGENERATE if a GSW/GS run enqueued
+ * since the last synchronising call met <|V|> = 0 (and clears the flag). */
+int hot_sync(hot_ctx* ctx);
+
+/* Host-only check of a problem description (no device work, usable without a GPU):
+ * slm fields, 1 <= M <= HOT_MAX_TRAPS, xyz finite (host M x 3), iters >= 0. */
+int hot_check_problem(const hot_slm* slm, int32_t M, const double* xyz, int32_t iters);
+
+/* ---- single hologram ---------------------------------------------------------------- */
+
+/* Random superposition, Eq. 3 with w_m = 1 (Section 3; Section 4 "SR holograms").
+ *   xyz     host, M x 3 trap positions (x_m, y_m, z_m) [m]
+ *   theta0  host, M trap phases [rad]; NULL draws them from `seed` with SplitMix64
+ *           (theta_m = 2 pi (z >> 40) 2^-24 for the m-th output z)
+ *   phase   device, N = nx*ny floats, out: phi_j
+ *   V       device, 2M floats, out: V_m of the mask (Eq. 1)
+ *   stats   host, 1 entry or NULL */
+int hot_rs(hot_ctx* ctx, const hot_slm* slm, int32_t M, const double* xyz, const double* theta0,
+           uint64_t seed, float* phase, float* V, hot_stats* stats);
+
+/* Gerchberg-Saxton: GSW below without the weight update (w_m = 1 throughout).
+ *   stats   host, iters+1 entries or NULL: entry k describes V of the k-th mask. */
+int hot_gs(hot_ctx* ctx, const hot_slm* slm, int32_t M, const double* xyz, const double* theta0,
+           uint64_t seed, int32_t iters, float* phase, float* V, hot_stats* stats);
+
+/* Weighted Gerchberg-Saxton (Section 3, Fig. 2), `iters` = K iterations:
+ *   w = w0 (or 1), theta = theta0, phi = backward(w, theta);
+ *   K times: V = forward(phi) -> stats[k]; w_m <- w_m <|V|>/|V_m|; theta_m <- arg V_m;
+ *            phi = backward(w, theta);
+ *   finally V = forward(phi) -> stats[K].
+ *   w0         device, M floats or NULL (all 1): warm start
+ *   w_out      device, M floats or NULL: the weights that produced the final phase
+ *   theta_out  device, M floats or NULL: the trap phases that produced the final phase
+ * Passing (theta_out, w_out) of a K1-iteration call back as (theta0, w0) and running K2
+ * more iterations reproduces a single K1+K2 call bit for bit. */
+int hot_gsw(hot_ctx* ctx, const hot_slm* slm, int32_t M, const double* xyz, const double* theta0,
+            uint64_t seed, int32_t iters, const float* w0, float* w_out, float* theta_out,
+            float* phase, float* V, hot_stats* stats);
+
+/* ---- batches of holograms sharing one SLM ------------------------------------------- */
+
+/* B independent GSW problems in one launch sequence.  Hologram b has M[b] traps; traps
+ * are concatenated in order (offset_b = M[0] + ... + M[b-1], total T = sum M).
+ *   M       host, B counts, each 1..HOT_MAX_TRAPS
+ *   xyz     host, T x 3;  theta0 host, T [rad] (required)
+ *   phase   device, B x N floats;  V device, 2T floats
+ *   stats   host, B x (iters+1) entries (hologram-major) or NULL
+ * Each hologram's result equals hot_gsw on that hologram alone (same kernels per pixel tile). */
+int hot_gsw_batched(hot_ctx* ctx, const hot_slm* slm, int32_t B, const int32_t* M, const double* xyz,
+                    const double* theta0, int32_t iters, float* phase, float* V, hot_stats* stats);
+
+/* Eq. 1 for B given masks: V of hologram b from phase[b] (device, B x N) -> V (device, 2T). */
+int hot_forward_V(hot_ctx* ctx, const hot_slm* slm, int32_t B, const int32_t* M, const double* xyz,
+                  const float* phase, float* V);
+
+/* Adjoint of Eq. 1: for a real loss L(V) and G_m = dL/dRe V_m + i dL/dIm V_m (device, 2T),
+ *   grad_phase[b][j] = dL/dphi_j = (1/N) Im( exp(-i phi_j) sum_m G_m exp(i Delta_j^m) ),
+ * with Delta recomputed (never stored).  phase device B x N, grad_phase device B x N. */
+int hot_adjoint(hot_ctx* ctx, const hot_slm* slm, int32_t B, const int32_t* M, const double* xyz,
+                const float* phase, const float* G, float* grad_phase);
+
+/* ---- diagnostics ---------------------------------------------------------------------- */
+
+/* Measurement aid for benchmarks and profilers: for the single-hologram problem given,
+ * launches four groups of kernels `reps` times each, back to back on the context's stream
+ * (current variant and tuning), each group bracketed by HIP events, and writes the mean
+ * device time per launch in milliseconds to
+ *   ms[0]  one GSW iteration's main kernel (on-the-fly: the fused update + pixel pass +
+ *          trap pass kernel; stored: the pixel pass and trap pass kernels)
+ *   ms[1]  the fixed-order reduction of the trap-pass partials into V
+ *   ms[2]  the pixel pass alone      ms[3]  the trap pass alone
+ * phase (device, N floats) and V (device, 2M floats) are scratch outputs.  Synchronises
+ * the stream. */
+int hot_time_passes(hot_ctx* ctx, const hot_slm* slm, int32_t M, const double* xyz, const double* theta0,
+                    int32_t reps, float* phase, float* V, float* ms);
+
+
+/* Message for the last non-OK return on this thread ("" if none). */
+const char* hot_last_error(void);
+int hot_abi_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HOT_H */

@@ -1,0 +1,732 @@
+// hot_api.cpp -- the C ABI declared in include/hot.h: argument checks, per-trap
+// coefficients (FP64 -> FP32, Eq. 2 in revolutions), trap-pass tiling, device buffers,
+// and the launch sequences of RS / GS / GSW (Section 3, Fig. 2), the batched solver,
+// Eq. 1 on its own and its adjoint.
+#include "hot.h"
+#include "hot_internal.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+using namespace hot;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return code;
+}
+
+#define HIP_TRY(expr)                                                                          \
+  do {                                                                                         \
+    hipError_t e_ = (expr);                                                                    \
+    if (e_ != hipSuccess)                                                                      \
+      return fail(e_ == hipErrorOutOfMemory ? HOT_ENOMEM : HOT_EDEVICE, "%s failed: %s (%s:%d)", \
+                  #expr, hipGetErrorString(e_), __FILE__, __LINE__);                             \
+  } while (0)
+
+struct DevBuf {
+  void* p = nullptr;
+  size_t cap = 0;
+};
+
+struct Staging {
+  void* host = nullptr;
+  size_t cap = 0;
+  hipEvent_t ev = nullptr;
+  bool pending = false;
+};
+
+constexpr int kRing = 8;
+constexpr double kPi = 3.14159265358979323846;
+
+}  // namespace
+
+struct hot_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  hipStream_t own_stream = nullptr;
+  int variant = HOT_ONTHEFLY;
+  int tune_q = 0, tune_tpl = 0, tune_seg = 0, tune_amax = 0;
+  DevBuf coef, st, hd, partial, stats, flag, amat, efield;
+  Staging ring[kRing];
+  int ring_pos = 0;
+  int* flag_host = nullptr;  // pinned
+  // identity of the trap tables now on the device (skips re-upload and stored-matrix rebuilds)
+  std::vector<double> key;
+  bool amat_valid = false;
+  std::vector<TrapCoef> h_coef;
+  std::vector<TrapState> h_st;
+  std::vector<HoloDesc> h_hd;
+};
+
+namespace {
+
+int set_dev(hot_ctx* c) {
+  HIP_TRY(hipSetDevice(c->device));
+  return HOT_OK;
+}
+
+int ensure(hot_ctx* c, DevBuf& b, size_t bytes) {
+  if (bytes <= b.cap) return HOT_OK;
+  if (b.p) {
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    HIP_TRY(hipFree(b.p));
+    b.p = nullptr;
+    b.cap = 0;
+  }
+  size_t want = std::max<size_t>(bytes, 256);
+  hipError_t e = hipMalloc(&b.p, want);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    b.p = nullptr;
+    return fail(HOT_ENOMEM, "device allocation of %zu bytes failed: %s", want, hipGetErrorString(e));
+  }
+  b.cap = want;
+  return HOT_OK;
+}
+
+// Asynchronous host-to-device copy through a ring of pinned staging buffers, so the
+// caller's host arrays may be reused as soon as the call returns.
+int upload(hot_ctx* c, void* dst, const void* src, size_t bytes) {
+  if (bytes == 0) return HOT_OK;
+  Staging& s = c->ring[c->ring_pos];
+  c->ring_pos = (c->ring_pos + 1) % kRing;
+  if (s.pending) {
+    HIP_TRY(hipEventSynchronize(s.ev));
+    s.pending = false;
+  }
+  if (s.cap < bytes) {
+    if (s.host) HIP_TRY(hipHostFree(s.host));
+    s.host = nullptr;
+    s.cap = 0;
+    size_t want = std::max<size_t>(bytes, 4096);
+    hipError_t e = hipHostMalloc(&s.host, want, hipHostMallocDefault);
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      return fail(HOT_ENOMEM, "pinned host allocation of %zu bytes failed", want);
+    }
+    s.cap = want;
+  }
+  memcpy(s.host, src, bytes);
+  HIP_TRY(hipMemcpyAsync(dst, s.host, bytes, hipMemcpyHostToDevice, c->stream));
+  HIP_TRY(hipEventRecord(s.ev, c->stream));
+  s.pending = true;
+  return HOT_OK;
+}
+
+bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
+
+int check_slm(const hot_slm* slm) {
+  if (!slm) return fail(HOT_EINVAL, "slm is NULL");
+  if (slm->nx < 1 || slm->ny < 1 || slm->nx > HOT_MAX_SIDE || slm->ny > HOT_MAX_SIDE)
+    return fail(HOT_EINVAL, "grid %d x %d outside 1..%d", slm->nx, slm->ny, HOT_MAX_SIDE);
+  if (!finite_pos(slm->pitch) || !finite_pos(slm->wavelength) || !finite_pos(slm->focal))
+    return fail(HOT_EINVAL, "pitch, wavelength and focal length must be finite and > 0");
+  return HOT_OK;
+}
+
+int check_traps(int32_t m, const double* xyz, const char* what) {
+  if (m < 1 || m > HOT_MAX_TRAPS) return fail(HOT_EINVAL, "%s: trap count %d outside 1..%d", what, m, HOT_MAX_TRAPS);
+  if (!xyz) return fail(HOT_EINVAL, "%s: xyz is NULL", what);
+  for (int64_t i = 0; i < 3LL * m; ++i)
+    if (!std::isfinite(xyz[i])) return fail(HOT_EINVAL, "%s: xyz[%lld] is not finite", what, (long long)i);
+  return HOT_OK;
+}
+
+uint64_t splitmix64_next(uint64_t& s) {
+  uint64_t z = (s += 0x9E3779B97F4A7C15ULL);
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
+  return z ^ (z >> 31);
+}
+
+// Trap-pass lane layout for a hologram of m traps on a row segment of len pixels, for a
+// block of W waves and tpl traps per lane: each wave = a slices x g trap lanes.  Returns an
+// estimate of the block's cycles: per chunk of g*tpl traps, every lane walks its slice
+// (slen pixels x tpl terms x 36 issue cycles, or the LDS read when tpl is small), then the
+// block syncs and sums the S = W*a slice partials of each trap.
+double layout_cost(int m, int len, int W, int tpl, int amax_cap, int& g, int& a) {
+  int amax = std::max(1, std::min(16, len / (8 * W)));
+  if (amax_cap > 0) amax = std::min(amax, amax_cap);
+  double best = 1e300;
+  g = 64;
+  a = 1;
+  for (int gg = 1; gg <= 64; ++gg) {
+    const int aa = std::min(64 / gg, amax);
+    const int S = W * aa;
+    const int slen = (len + S - 1) / S;
+    const int chunks = (m + gg * tpl - 1) / (gg * tpl);
+    const int outs_per_thread = (gg * tpl + 64 * W - 1) / (64 * W);
+    const double step = std::max(36.0 * tpl, 32.0);
+    const double cost = chunks * (slen * step + 500.0 + 12.0 * S * outs_per_thread);
+    if (cost < best - 1e-9) {
+      best = cost;
+      g = gg;
+      a = aa;
+    }
+  }
+  return best;
+}
+
+const int kTplChoices[] = {1, 2, 3, 4, 5, 6, 8};
+
+// One traps-per-lane count for the whole launch (it is a template parameter of the kernel):
+// the one with the least summed cost over the holograms.
+int choose_tpl(const int32_t* counts, int B, int len, int W, int amax_cap) {
+  int best_t = 1;
+  double best = 1e300;
+  for (int t : kTplChoices) {
+    double cost = 0.0;
+    for (int b = 0; b < B; ++b) {
+      int g, a;
+      cost += layout_cost(counts[b], len, W, t, amax_cap, g, a);
+    }
+    if (cost < best) {
+      best = cost;
+      best_t = t;
+    }
+  }
+  return best_t;
+}
+
+struct Plan {
+  int B = 0, T = 0, mmax = 0, nx = 0, ny = 0, n = 0;
+  bool fract = false;
+  // fused iteration kernel: row segments of <= nt*q pixels, nt threads, q pixels per lane
+  FwdGeom fg{};
+  int nt = 256, q = 1, tpl = 1;
+  // stand-alone trap pass (hot_forward_V): row segments of <= kSegMax pixels, kBlock threads
+  FwdGeom fgf{};
+  int tplf = 1;
+  int nblk_stored = 0;
+};
+
+FwdGeom row_segments(int nx, int ny, int segmax) {
+  FwdGeom f;
+  f.nx = nx;
+  f.ny = ny;
+  f.nseg = (nx + segmax - 1) / segmax;
+  f.seg_w = (nx + f.nseg - 1) / f.nseg;
+  return f;
+}
+
+// Build coefficient, state and descriptor tables on the host.
+int prepare(hot_ctx* c, const hot_slm* slm, int B, const int32_t* counts, const double* xyz, const double* theta0,
+            bool seeded, uint64_t seed, Plan& P) {
+  P.B = B;
+  P.nx = slm->nx;
+  P.ny = slm->ny;
+  P.n = slm->nx * slm->ny;
+  P.T = 0;
+  P.mmax = 0;
+  for (int b = 0; b < B; ++b) {
+    P.T += counts[b];
+    P.mmax = std::max(P.mmax, (int)counts[b]);
+  }
+  // fused kernel shape
+  {
+    const int q = c->tune_q == 2 ? 2 : 1;
+    int segmax = 512 * q;
+    if (c->tune_seg > 0) segmax = std::min(segmax, c->tune_seg);
+    P.fg = row_segments(slm->nx, slm->ny, segmax);
+    P.q = (c->tune_q == 0 && P.fg.seg_w > 512) ? 2 : q;
+    P.nt = P.fg.seg_w <= 256 * P.q ? 256 : 512;
+  }
+  P.fgf = row_segments(slm->nx, slm->ny, c->tune_seg > 0 ? c->tune_seg : kSegMax);
+  P.nblk_stored = stored_nblk(P.n);
+
+  const double lf = slm->wavelength * slm->focal;
+  const double ca = slm->pitch / (2.0 * lf);
+  const double cg = slm->pitch * slm->pitch / (8.0 * lf * slm->focal);
+  c->h_coef.resize(P.T);
+  c->h_st.resize(P.T);
+  c->h_hd.resize(2 * (size_t)B);
+  const double umax = slm->nx - 1, vmax = slm->ny - 1;
+  double bound = 0.0, thmax = 1.0;
+  uint64_t sm = seed;
+  for (int t = 0; t < P.T; ++t) {
+    const double x = xyz[3 * t], y = xyz[3 * t + 1], z = xyz[3 * t + 2];
+    TrapCoef k;
+    k.a = (float)(ca * x);
+    k.b = (float)(ca * y);
+    k.g = (float)(cg * z);
+    k.pad = 0.0f;
+    c->h_coef[t] = k;
+    bound = std::max(bound, std::fabs((double)k.g) * (umax * umax + vmax * vmax) + std::fabs((double)k.a) * umax +
+                                std::fabs((double)k.b) * vmax);
+    double th;
+    if (seeded)
+      th = 2.0 * kPi * (double)(splitmix64_next(sm) >> 40) * (1.0 / 16777216.0);
+    else
+      th = theta0[t];
+    if (!std::isfinite(th)) return fail(HOT_EINVAL, "theta0[%d] is not finite", t);
+    TrapState s;
+    s.theta_rad = (float)th;
+    s.theta_rev = s.theta_rad * 0.159154943091895336f;
+    s.w = 1.0f;
+    s.pad = 0.0f;
+    thmax = std::max(thmax, std::fabs((double)s.theta_rev));
+    c->h_st[t] = s;
+  }
+  // keep |argument| of the hardware sin/cos inside its domain (|x| < 256 rev)
+  P.fract = bound + thmax + 2.0 > 240.0;
+  const int Wi = P.nt / 64, Wf = kBlock / 64;
+  P.tpl = c->tune_tpl > 0 ? c->tune_tpl : choose_tpl(counts, B, P.fg.seg_w, Wi, c->tune_amax);
+  P.tplf = c->tune_tpl > 0 ? c->tune_tpl : choose_tpl(counts, B, P.fgf.seg_w, Wf, c->tune_amax);
+  int off = 0;
+  for (int b = 0; b < B; ++b) {
+    HoloDesc h{};
+    h.m = counts[b];
+    h.off = off;
+    h.tpl = P.tpl;
+    layout_cost(h.m, P.fg.seg_w, Wi, P.tpl, c->tune_amax, h.g, h.a);
+    c->h_hd[b] = h;
+    h.tpl = P.tplf;
+    layout_cost(h.m, P.fgf.seg_w, Wf, P.tplf, c->tune_amax, h.g, h.a);
+    c->h_hd[B + b] = h;
+    off += counts[b];
+  }
+  return HOT_OK;
+}
+
+// Device tables: coef [T], hd [2B] (fused-kernel layouts, then stand-alone trap-pass
+// layouts), state [2T] (double buffer: iteration k reads one half and writes the other).
+int upload_tables(hot_ctx* c, const hot_slm* slm, const Plan& P, const double* xyz, const int32_t* counts,
+                  bool with_state = true) {
+  std::vector<double> key;
+  key.reserve(10 + P.B + 3 * (size_t)P.T);
+  key.push_back(slm->nx);
+  key.push_back(slm->ny);
+  key.push_back(slm->pitch);
+  key.push_back(slm->wavelength);
+  key.push_back(slm->focal);
+  key.push_back(c->tune_q);
+  key.push_back(c->tune_tpl);
+  key.push_back(c->tune_seg);
+  key.push_back(c->tune_amax);
+  key.push_back(P.B);
+  for (int b = 0; b < P.B; ++b) key.push_back(counts[b]);
+  key.insert(key.end(), xyz, xyz + 3 * (size_t)P.T);
+  int rc;
+  if ((rc = ensure(c, c->st, 2 * sizeof(TrapState) * P.T))) return rc;
+  if (with_state && (rc = upload(c, c->st.p, c->h_st.data(), sizeof(TrapState) * P.T))) return rc;
+  if (key == c->key && c->coef.p && c->hd.p) return HOT_OK;
+  c->key.clear();
+  c->amat_valid = false;
+  if ((rc = ensure(c, c->coef, sizeof(TrapCoef) * P.T))) return rc;
+  if ((rc = ensure(c, c->hd, sizeof(HoloDesc) * 2 * P.B))) return rc;
+  if ((rc = upload(c, c->coef.p, c->h_coef.data(), sizeof(TrapCoef) * P.T))) return rc;
+  if ((rc = upload(c, c->hd.p, c->h_hd.data(), sizeof(HoloDesc) * 2 * P.B))) return rc;
+  c->key.swap(key);
+  return HOT_OK;
+}
+
+// Read the device degenerate flag (after a stream sync) and clear it.
+int take_flag(hot_ctx* c) {
+  HIP_TRY(hipMemcpyAsync(c->flag_host, c->flag.p, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  if (*c->flag_host) {
+    HIP_TRY(launch_fill_u32(c->stream, (unsigned*)c->flag.p, 0u, 1));
+    return fail(HOT_EDEGENERATE, "GSW/GS met <|V|> = 0: the phase mask sends no light to any trap");
+  }
+  return HOT_OK;
+}
+
+enum Algo { kRS = 0, kGS = 1, kGSW = 2 };
+
+int ensure_stored(hot_ctx* c, const Plan& P) {
+  int rc;
+  if ((rc = ensure(c, c->efield, sizeof(float2) * (size_t)P.B * P.n))) return rc;
+  if (!c->amat_valid || c->amat.cap < sizeof(float2) * (size_t)P.T * P.n) {
+    if ((rc = ensure(c, c->amat, sizeof(float2) * (size_t)P.T * P.n))) return rc;
+    HIP_TRY(launch_expdelta(c->stream, P.nx, P.ny, P.B, P.mmax, P.fract, (const TrapCoef*)c->coef.p,
+                            (const HoloDesc*)c->hd.p, (float2*)c->amat.p));
+    c->amat_valid = true;
+  }
+  return HOT_OK;
+}
+
+IterArgs iter_args(hot_ctx* c, const Plan& P, float* phase, int K) {
+  IterArgs a;
+  a.fg = P.fg;
+  a.B = P.B;
+  a.nt = P.nt;
+  a.q = P.q;
+  a.tpl = P.tpl;
+  a.fract = P.fract;
+  a.coef = (const TrapCoef*)c->coef.p;
+  a.hd = (const HoloDesc*)c->hd.p;
+  a.stats = (float*)c->stats.p;
+  a.stat_stride = K + 1;
+  a.flag = (int*)c->flag.p;
+  a.phase = phase;
+  a.partial = (float2*)c->partial.p;
+  return a;
+}
+
+int solve(hot_ctx* c, const hot_slm* slm, int B, const int32_t* counts, const double* xyz, const double* theta0,
+          bool seeded, uint64_t seed, int algo, int iters, const float* w0, float* w_out, float* theta_out,
+          float* phase, float* V, hot_stats* stats, int variant) {
+  int rc;
+  if ((rc = set_dev(c))) return rc;
+  Plan P;
+  if ((rc = prepare(c, slm, B, counts, xyz, theta0, seeded, seed, P))) return rc;
+  const int K = algo == kRS ? 0 : iters;
+  const bool stored = variant == HOT_STORED;
+  const int nblk = stored ? P.nblk_stored : P.fg.nblk();
+  if ((rc = upload_tables(c, slm, P, xyz, counts))) return rc;
+  if ((rc = ensure(c, c->partial, sizeof(float2) * (size_t)P.T * nblk))) return rc;
+  if ((rc = ensure(c, c->stats, sizeof(float) * 3 * (size_t)B * (K + 1)))) return rc;
+  if (stored && (rc = ensure_stored(c, P))) return rc;
+  TrapState* st[2] = {(TrapState*)c->st.p, (TrapState*)c->st.p + P.T};
+  if (w0) HIP_TRY(launch_import_w(c->stream, w0, st[0], P.T));
+
+  const HoloDesc* hd = (const HoloDesc*)c->hd.p;
+  float2* part = (float2*)c->partial.p;
+  float* dstats = (float*)c->stats.p;
+  const float inv_n = (float)(1.0 / (double)P.n);
+  const int upd = algo == kGSW ? 2 : 1;
+
+  if (!stored) {
+    IterArgs a = iter_args(c, P, phase, K);
+    for (int k = 0; k <= K; ++k) {
+      a.upd = k == 0 ? 0 : upd;
+      a.st_in = k == 0 ? st[0] : st[(k - 1) & 1];
+      a.st_out = st[k & 1];
+      a.Vprev = V;
+      a.kstat = k - 1;
+      HIP_TRY(launch_iter(c->stream, a));
+      HIP_TRY(launch_reduce(c->stream, B, P.mmax, nblk, inv_n, part, hd, V));
+    }
+  } else {
+    for (int k = 0; k <= K; ++k) {
+      if (k > 0)
+        HIP_TRY(launch_update(c->stream, B, V, hd, st[(k - 1) & 1], st[k & 1], dstats, k - 1, K + 1, upd,
+                              (int*)c->flag.p));
+      HIP_TRY(launch_backward_stored(c->stream, P.n, B, (const float2*)c->amat.p, st[k & 1], hd, phase,
+                                     (float2*)c->efield.p));
+      HIP_TRY(launch_forward_stored(c->stream, P.n, B, (const float2*)c->amat.p, (const float2*)c->efield.p, hd,
+                                    part));
+      HIP_TRY(launch_reduce(c->stream, B, P.mmax, nblk, inv_n, part, hd, V));
+    }
+  }
+  HIP_TRY(launch_update(c->stream, B, V, hd, st[K & 1], st[K & 1], dstats, K, K + 1, 0, (int*)c->flag.p));
+  if (w_out || theta_out) HIP_TRY(launch_export_state(c->stream, st[K & 1], P.T, w_out, theta_out));
+  if (stats) {
+    HIP_TRY(hipMemcpyAsync(stats, dstats, sizeof(float) * 3 * (size_t)B * (K + 1), hipMemcpyDeviceToHost,
+                           c->stream));
+    return take_flag(c);
+  }
+  return HOT_OK;
+}
+
+int check_batch(const hot_slm* slm, int32_t B, const int32_t* M, const double* xyz, int64_t& T) {
+  int rc;
+  if ((rc = check_slm(slm))) return rc;
+  if (B < 1 || B > HOT_MAX_BATCH) return fail(HOT_EINVAL, "batch size %d outside 1..%d", B, HOT_MAX_BATCH);
+  if (!M) return fail(HOT_EINVAL, "M (trap counts) is NULL");
+  T = 0;
+  for (int b = 0; b < B; ++b) {
+    if (M[b] < 1 || M[b] > HOT_MAX_TRAPS)
+      return fail(HOT_EINVAL, "hologram %d: trap count %d outside 1..%d", b, M[b], HOT_MAX_TRAPS);
+    T += M[b];
+  }
+  if (T > (1LL << 24)) return fail(HOT_EINVAL, "total trap count %lld too large", (long long)T);
+  if (!xyz) return fail(HOT_EINVAL, "xyz is NULL");
+  for (int64_t i = 0; i < 3 * T; ++i)
+    if (!std::isfinite(xyz[i])) return fail(HOT_EINVAL, "xyz[%lld] is not finite", (long long)i);
+  return HOT_OK;
+}
+
+}  // namespace
+
+// ===================================================================== C ABI
+
+extern "C" {
+
+const char* hot_last_error(void) { return g_err.c_str(); }
+
+int hot_abi_version(void) { return HOT_ABI_VERSION; }
+
+int hot_check_problem(const hot_slm* slm, int32_t M, const double* xyz, int32_t iters) {
+  int rc;
+  if ((rc = check_slm(slm))) return rc;
+  if ((rc = check_traps(M, xyz, "problem"))) return rc;
+  if (iters < 0) return fail(HOT_EINVAL, "iters = %d < 0", iters);
+  return HOT_OK;
+}
+
+int hot_create(hot_ctx** out, int device, void* stream) {
+  if (!out) return fail(HOT_EINVAL, "out is NULL");
+  *out = nullptr;
+  int n = 0;
+  hipError_t e = hipGetDeviceCount(&n);
+  if (e != hipSuccess || n <= 0) {
+    (void)hipGetLastError();
+    return fail(HOT_EDEVICE, "no HIP device available (%s)", e == hipSuccess ? "count 0" : hipGetErrorString(e));
+  }
+  if (device < 0 || device >= n) return fail(HOT_EINVAL, "device %d outside 0..%d", device, n - 1);
+  hot_ctx* c = new (std::nothrow) hot_ctx();
+  if (!c) return fail(HOT_ENOMEM, "context allocation failed");
+  c->device = device;
+  auto bail = [&](int code) {
+    hot_destroy(c);
+    return code;
+  };
+  if (hipSetDevice(device) != hipSuccess) return bail(fail(HOT_EDEVICE, "hipSetDevice(%d) failed", device));
+  if (hipStreamCreateWithFlags(&c->own_stream, hipStreamNonBlocking) != hipSuccess)
+    return bail(fail(HOT_EDEVICE, "stream creation failed"));
+  c->stream = (hipStream_t)stream;
+  for (auto& s : c->ring)
+    if (hipEventCreateWithFlags(&s.ev, hipEventDisableTiming) != hipSuccess)
+      return bail(fail(HOT_EDEVICE, "event creation failed"));
+  if (hipHostMalloc((void**)&c->flag_host, sizeof(int), hipHostMallocDefault) != hipSuccess)
+    return bail(fail(HOT_ENOMEM, "pinned flag allocation failed"));
+  *c->flag_host = 0;
+  int rc = ensure(c, c->flag, sizeof(int));
+  if (rc) return bail(rc);
+  if (launch_fill_u32(c->stream, (unsigned*)c->flag.p, 0u, 1) != hipSuccess)
+    return bail(fail(HOT_EDEVICE, "flag initialisation failed"));
+  *out = c;
+  return HOT_OK;
+}
+
+int hot_destroy(hot_ctx* c) {
+  if (!c) return HOT_OK;
+  (void)hipSetDevice(c->device);
+  (void)hipStreamSynchronize(c->stream);
+  for (DevBuf* b : {&c->coef, &c->st, &c->hd, &c->partial, &c->stats, &c->flag, &c->amat, &c->efield})
+    if (b->p) (void)hipFree(b->p);
+  for (auto& s : c->ring) {
+    if (s.pending && s.ev) (void)hipEventSynchronize(s.ev);
+    if (s.host) (void)hipHostFree(s.host);
+    if (s.ev) (void)hipEventDestroy(s.ev);
+  }
+  if (c->flag_host) (void)hipHostFree(c->flag_host);
+  if (c->own_stream) (void)hipStreamDestroy(c->own_stream);
+  delete c;
+  return HOT_OK;
+}
+
+int hot_set_stream(hot_ctx* c, void* stream) {
+  if (!c) return fail(HOT_EINVAL, "ctx is NULL");
+  c->stream = (hipStream_t)stream;
+  return HOT_OK;
+}
+
+int hot_set_variant(hot_ctx* c, int variant) {
+  if (!c) return fail(HOT_EINVAL, "ctx is NULL");
+  if (variant != HOT_ONTHEFLY && variant != HOT_STORED) return fail(HOT_EINVAL, "unknown variant %d", variant);
+  c->variant = variant;
+  return HOT_OK;
+}
+
+int hot_set_tuning(hot_ctx* c, int key, int value) {
+  if (!c) return fail(HOT_EINVAL, "ctx is NULL");
+  switch (key) {
+    case HOT_TUNE_PIXELS_PER_LANE:
+      if (value != 0 && value != 1 && value != 2 && value != 4) return fail(HOT_EINVAL, "pixels per lane must be 1, 2 or 4");
+      c->tune_q = value;
+      return HOT_OK;
+    case HOT_TUNE_TRAPS_PER_LANE:
+      if (value < 0 || value > kTplMax) return fail(HOT_EINVAL, "traps per lane must be 0..%d", kTplMax);
+      c->tune_tpl = value;
+      return HOT_OK;
+    case HOT_TUNE_SEGMENT:
+      if (value != 0 && (value < 64 || value > 1024)) return fail(HOT_EINVAL, "segment must be 0 or 64..1024");
+      c->tune_seg = value;
+      return HOT_OK;
+    case HOT_TUNE_SLICES:
+      if (value < 0 || value > 16) return fail(HOT_EINVAL, "slices must be 0..16");
+      c->tune_amax = value;
+      return HOT_OK;
+    default:
+      return fail(HOT_EINVAL, "unknown tuning key %d", key);
+  }
+}
+
+int hot_sync(hot_ctx* c) {
+  if (!c) return fail(HOT_EINVAL, "ctx is NULL");
+  int rc;
+  if ((rc = set_dev(c))) return rc;
+  return take_flag(c);
+}
+
+static int single(hot_ctx* c, const hot_slm* slm, int32_t M, const double* xyz, const double* theta0, uint64_t seed,
+                  int algo, int32_t iters, const float* w0, float* w_out, float* theta_out, float* phase, float* V,
+                  hot_stats* stats) {
+  if (!c) return fail(HOT_EINVAL, "ctx is NULL");
+  int rc;
+  if ((rc = hot_check_problem(slm, M, xyz, iters))) return rc;
+  if (!phase || !V) return fail(HOT_EINVAL, "phase and V output pointers are required");
+  return solve(c, slm, 1, &M, xyz, theta0, theta0 == nullptr, seed, algo, iters, w0, w_out, theta_out, phase, V,
+               stats, c->variant);
+}
+
+int hot_rs(hot_ctx* c, const hot_slm* slm, int32_t M, const double* xyz, const double* theta0, uint64_t seed,
+           float* phase, float* V, hot_stats* stats) {
+  return single(c, slm, M, xyz, theta0, seed, kRS, 0, nullptr, nullptr, nullptr, phase, V, stats);
+}
+
+int hot_gs(hot_ctx* c, const hot_slm* slm, int32_t M, const double* xyz, const double* theta0, uint64_t seed,
+           int32_t iters, float* phase, float* V, hot_stats* stats) {
+  return single(c, slm, M, xyz, theta0, seed, kGS, iters, nullptr, nullptr, nullptr, phase, V, stats);
+}
+
+int hot_gsw(hot_ctx* c, const hot_slm* slm, int32_t M, const double* xyz, const double* theta0, uint64_t seed,
+            int32_t iters, const float* w0, float* w_out, float* theta_out, float* phase, float* V,
+            hot_stats* stats) {
+  return single(c, slm, M, xyz, theta0, seed, kGSW, iters, w0, w_out, theta_out, phase, V, stats);
+}
+
+int hot_gsw_batched(hot_ctx* c, const hot_slm* slm, int32_t B, const int32_t* M, const double* xyz,
+                    const double* theta0, int32_t iters, float* phase, float* V, hot_stats* stats) {
+  if (!c) return fail(HOT_EINVAL, "ctx is NULL");
+  int64_t T;
+  int rc;
+  if ((rc = check_batch(slm, B, M, xyz, T))) return rc;
+  if (iters < 0) return fail(HOT_EINVAL, "iters = %d < 0", iters);
+  if (!theta0) return fail(HOT_EINVAL, "theta0 is required for batched calls");
+  if (!phase || !V) return fail(HOT_EINVAL, "phase and V output pointers are required");
+  return solve(c, slm, B, M, xyz, theta0, false, 0, kGSW, iters, nullptr, nullptr, nullptr, phase, V, stats,
+               HOT_ONTHEFLY);
+}
+
+int hot_forward_V(hot_ctx* c, const hot_slm* slm, int32_t B, const int32_t* M, const double* xyz,
+                  const float* phase, float* V) {
+  if (!c) return fail(HOT_EINVAL, "ctx is NULL");
+  int64_t T;
+  int rc;
+  if ((rc = check_batch(slm, B, M, xyz, T))) return rc;
+  if (!phase || !V) return fail(HOT_EINVAL, "phase and V pointers are required");
+  if ((rc = set_dev(c))) return rc;
+  Plan P;
+  std::vector<double> zeros(T, 0.0);
+  if ((rc = prepare(c, slm, B, M, xyz, zeros.data(), false, 0, P))) return rc;
+  if ((rc = upload_tables(c, slm, P, xyz, M, false))) return rc;
+  const int nblk = P.fgf.nblk();
+  if ((rc = ensure(c, c->partial, sizeof(float2) * (size_t)P.T * nblk))) return rc;
+  const HoloDesc* hdf = (const HoloDesc*)c->hd.p + B;
+  HIP_TRY(launch_forward(c->stream, P.fgf, B, P.tplf, P.fract, (const TrapCoef*)c->coef.p, hdf, phase,
+                         (float2*)c->partial.p));
+  HIP_TRY(launch_reduce(c->stream, B, P.mmax, nblk, (float)(1.0 / (double)P.n), (const float2*)c->partial.p, hdf, V));
+  return HOT_OK;
+}
+
+int hot_adjoint(hot_ctx* c, const hot_slm* slm, int32_t B, const int32_t* M, const double* xyz, const float* phase,
+                const float* G, float* grad_phase) {
+  if (!c) return fail(HOT_EINVAL, "ctx is NULL");
+  int64_t T;
+  int rc;
+  if ((rc = check_batch(slm, B, M, xyz, T))) return rc;
+  if (!phase || !G || !grad_phase) return fail(HOT_EINVAL, "phase, G and grad_phase pointers are required");
+  if ((rc = set_dev(c))) return rc;
+  Plan P;
+  std::vector<double> zeros(T, 0.0);
+  if ((rc = prepare(c, slm, B, M, xyz, zeros.data(), false, 0, P))) return rc;
+  if ((rc = upload_tables(c, slm, P, xyz, M, false))) return rc;
+  HIP_TRY(launch_backward(c->stream, P.nx, P.ny, B, P.fract, 1, (const TrapCoef*)c->coef.p, nullptr,
+                          (const HoloDesc*)c->hd.p, const_cast<float*>(phase), 1, G, grad_phase));
+  return HOT_OK;
+}
+
+int hot_time_passes(hot_ctx* c, const hot_slm* slm, int32_t M, const double* xyz, const double* theta0,
+                    int32_t reps, float* phase, float* V, float* ms) {
+  if (!c) return fail(HOT_EINVAL, "ctx is NULL");
+  int rc;
+  if ((rc = hot_check_problem(slm, M, xyz, 0))) return rc;
+  if (!theta0 || !phase || !V || !ms) return fail(HOT_EINVAL, "theta0, phase, V and ms are required");
+  if (reps < 1) return fail(HOT_EINVAL, "reps = %d < 1", reps);
+  if ((rc = set_dev(c))) return rc;
+  Plan P;
+  if ((rc = prepare(c, slm, 1, &M, xyz, theta0, false, 0, P))) return rc;
+  const bool stored = c->variant == HOT_STORED;
+  const int nblk = stored ? P.nblk_stored : std::max(P.fg.nblk(), P.fgf.nblk());
+  if ((rc = upload_tables(c, slm, P, xyz, &M))) return rc;
+  if ((rc = ensure(c, c->partial, sizeof(float2) * (size_t)P.T * nblk))) return rc;
+  if ((rc = ensure(c, c->stats, sizeof(float) * 3 * 2))) return rc;
+  if (stored && (rc = ensure_stored(c, P))) return rc;
+  const TrapCoef* coef = (const TrapCoef*)c->coef.p;
+  TrapState* st[2] = {(TrapState*)c->st.p, (TrapState*)c->st.p + P.T};
+  const HoloDesc* hd = (const HoloDesc*)c->hd.p;
+  float2* part = (float2*)c->partial.p;
+  const float inv_n = (float)(1.0 / (double)P.n);
+  // group 0: one GSW iteration's main kernel (fused passes, or the stored pixel + trap pass)
+  IterArgs a = iter_args(c, P, phase, 1);
+  a.upd = 2;
+  a.st_in = st[0];
+  a.st_out = st[1];
+  a.Vprev = V;
+  auto g0 = [&]() -> hipError_t {
+    if (!stored) return launch_iter(c->stream, a);
+    hipError_t e = launch_backward_stored(c->stream, P.n, 1, (const float2*)c->amat.p, st[0], hd, phase,
+                                          (float2*)c->efield.p);
+    if (e != hipSuccess) return e;
+    return launch_forward_stored(c->stream, P.n, 1, (const float2*)c->amat.p, (const float2*)c->efield.p, hd, part);
+  };
+  auto g1 = [&]() {
+    return launch_reduce(c->stream, 1, P.mmax, stored ? P.nblk_stored : P.fg.nblk(), inv_n, part, hd, V);
+  };
+  auto g2 = [&]() {
+    return stored ? launch_backward_stored(c->stream, P.n, 1, (const float2*)c->amat.p, st[0], hd, phase,
+                                           (float2*)c->efield.p)
+                  : launch_backward(c->stream, P.nx, P.ny, 1, P.fract, 1, coef, st[0], hd, phase, 0, nullptr, nullptr);
+  };
+  auto g3 = [&]() {
+    return stored ? launch_forward_stored(c->stream, P.n, 1, (const float2*)c->amat.p, (const float2*)c->efield.p, hd,
+                                          part)
+                  : launch_forward(c->stream, P.fgf, 1, P.tplf, P.fract, coef, hd + 1, phase, part);
+  };
+  hipEvent_t ev[5];
+  for (auto& e : ev) HIP_TRY(hipEventCreate(&e));
+  int out = HOT_OK;
+  do {
+    // V must hold a real trap field before the fused kernel's update reads it
+    if (g2() != hipSuccess || g3() != hipSuccess ||
+        launch_reduce(c->stream, 1, P.mmax, stored ? P.nblk_stored : P.fgf.nblk(), inv_n, part,
+                      stored ? hd : hd + 1, V) != hipSuccess ||
+        g0() != hipSuccess || g1() != hipSuccess) {
+      out = fail(HOT_EDEVICE, "launch failed");
+      break;
+    }
+    (void)hipEventRecord(ev[0], c->stream);
+    for (int i = 0; i < reps && out == HOT_OK; ++i) if (g0() != hipSuccess) out = fail(HOT_EDEVICE, "launch failed");
+    (void)hipEventRecord(ev[1], c->stream);
+    for (int i = 0; i < reps && out == HOT_OK; ++i) if (g1() != hipSuccess) out = fail(HOT_EDEVICE, "launch failed");
+    (void)hipEventRecord(ev[2], c->stream);
+    for (int i = 0; i < reps && out == HOT_OK; ++i) if (g2() != hipSuccess) out = fail(HOT_EDEVICE, "launch failed");
+    (void)hipEventRecord(ev[3], c->stream);
+    for (int i = 0; i < reps && out == HOT_OK; ++i) if (g3() != hipSuccess) out = fail(HOT_EDEVICE, "launch failed");
+    (void)hipEventRecord(ev[4], c->stream);
+    if (out != HOT_OK) break;
+    if (hipEventSynchronize(ev[4]) != hipSuccess) {
+      out = fail(HOT_EDEVICE, "event sync failed");
+      break;
+    }
+    for (int k = 0; k < 4; ++k) {
+      float t = 0.0f;
+      (void)hipEventElapsedTime(&t, ev[k], ev[k + 1]);
+      ms[k] = t / (float)reps;
+    }
+  } while (0);
+  for (auto& e : ev) (void)hipEventDestroy(e);
+  return out;
+}
+
+}  // extern "C"

@@ -1,0 +1,113 @@
+// hot_internal.h -- device data layout and kernel launchers shared by hot_kernels.hip
+// and hot_api.cpp (the C ABI).  Not part of the public interface.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace hot {
+
+// Phases inside the kernels are in revolutions (1 rev = 2 pi rad), which makes the
+// reduction of a phase to one period exact (fract of an FP32 value is exact) and
+// matches the input convention of the hardware sin/cos (sin(2 pi x)).
+//
+// Pixel coordinates are carried as exact integers in FP32:
+//   U_c = 2c - (nx-1),  V_r = 2r - (ny-1)  (so x = U pitch / 2, y = V pitch / 2),
+// and Eq. 2 divided by 2 pi becomes  Delta_rev = g (U^2 + V^2) + a U + b V  with
+//   a = pitch x_m / (2 lambda f),  b = pitch y_m / (2 lambda f),  g = pitch^2 z_m / (8 lambda f^2).
+// U^2 and V^2 are exact in FP32 for nx, ny <= 4096.
+
+// Per-trap constant coefficients, formed in FP64 on the host, rounded once.
+struct alignas(16) TrapCoef {
+  float a, b, g, pad;
+};
+
+// Per-trap iteration state, rewritten on the device by the weight/phase update.
+struct alignas(16) TrapState {
+  float theta_rev;  // theta_m / (2 pi), FP32 product of theta_rad and FP32(1/(2 pi))
+  float w;          // GSW weight
+  float theta_rad;  // theta_m in radians (what the caller sees)
+  float pad;
+};
+
+// Per-hologram launch description for batched problems (device array, one per hologram).
+struct alignas(16) HoloDesc {
+  int32_t m;      // traps in this hologram
+  int32_t off;    // offset of its first trap in the concatenated tables
+  int32_t g;      // trap pass: trap lanes per slice
+  int32_t a;      // trap pass: slices per wave
+  int32_t tpl;    // trap pass: traps per lane per chunk (the launch's TPL)
+  int32_t pad0, pad1, pad2;
+};
+
+constexpr int kTplMax = 8;     // traps per lane in the trap pass: 1..6 or 8
+constexpr int kBlock = 256;    // threads of the stand-alone pass kernels
+constexpr int kMaxTraps = 2048;
+constexpr int kSegMax = 1024;  // pixels of a row per trap-pass block
+constexpr int kStoredPpl = 8;  // stored variant: pixels per lane of the trap pass
+inline int stored_nblk(int n) { return (n + 64 * kStoredPpl - 1) / (64 * kStoredPpl); }
+
+// Row-segment tiling of the trap pass (and of the fused iteration kernel).
+struct FwdGeom {
+  int nx, ny;
+  int seg_w;  // pixels per row segment (block)
+  int nseg;   // segments per row
+  int nblk() const { return nseg * ny; }
+};
+
+// One fused iteration: (optional GS/GSW update) -> pixel pass -> trap pass partials.
+struct IterArgs {
+  FwdGeom fg;
+  int B = 1;
+  int nt = 256, q = 1, tpl = 1;  // block threads (256/512), pixels per lane (1/2), traps per lane
+  bool fract = false;
+  const TrapCoef* coef = nullptr;
+  const HoloDesc* hd = nullptr;
+  const TrapState* st_in = nullptr;
+  TrapState* st_out = nullptr;
+  const float* Vprev = nullptr;  // interleaved V of the previous mask (upd != 0)
+  float* stats = nullptr;
+  int kstat = 0, stat_stride = 1;
+  int upd = 0;                   // 0 none, 1 GS, 2 GSW
+  int* flag = nullptr;
+  float* phase = nullptr;
+  float2* partial = nullptr;
+};
+
+// ---- launchers (hot_kernels.hip); all enqueue on `s` and return hipError_t ----
+
+hipError_t launch_iter(hipStream_t s, const IterArgs& a);
+
+// Pixel pass alone (Eq. 3 with weights).  mode 0 writes the phase; mode 1 (adjoint) reads
+// `phase` and G (2T floats, interleaved) and writes grad[b][j] = (1/N) Im(e^{-i phi_j} sum_m G_m e^{i Delta_j^m}).
+hipError_t launch_backward(hipStream_t s, int nx, int ny, int B, bool fract, int q, const TrapCoef* coef,
+                           const TrapState* st, const HoloDesc* hd, float* phase, int mode, const float* G,
+                           float* grad);
+
+// Trap pass alone: per-block partial sums of e^{i 2pi (phi - Delta)} -> partial[(off + m) * nblk + blk].
+// `tpl` is the traps-per-lane count every hologram of the launch was laid out for.
+hipError_t launch_forward(hipStream_t s, const FwdGeom& fg, int B, int tpl, bool fract, const TrapCoef* coef,
+                          const HoloDesc* hd, const float* phase, float2* partial);
+
+// Fixed-order sum of the partials: V (interleaved re/im) = sum / N.
+hipError_t launch_reduce(hipStream_t s, int B, int mmax, int nblk, float inv_n, const float2* partial,
+                         const HoloDesc* hd, float* V);
+
+// One block per hologram: stats[b][kstat] from V and, for mode 1 (GS) / 2 (GSW), the update st_in -> st_out.
+hipError_t launch_update(hipStream_t s, int B, const float* V, const HoloDesc* hd, const TrapState* st_in,
+                         TrapState* st_out, float* stats, int kstat, int stat_stride, int mode, int* flag);
+
+// Stored-exp(i Delta) variant.
+hipError_t launch_expdelta(hipStream_t s, int nx, int ny, int B, int mmax, bool fract, const TrapCoef* coef,
+                           const HoloDesc* hd, float2* A);
+hipError_t launch_backward_stored(hipStream_t s, int n, int B, const float2* A, const TrapState* st,
+                                  const HoloDesc* hd, float* phase, float2* E);
+hipError_t launch_forward_stored(hipStream_t s, int n, int B, const float2* A, const float2* E, const HoloDesc* hd,
+                                 float2* partial);
+
+// Small helpers.
+hipError_t launch_fill_u32(hipStream_t s, unsigned* p, unsigned v, int n);
+hipError_t launch_export_state(hipStream_t s, const TrapState* st, int t, float* w_out, float* theta_out);
+hipError_t launch_import_w(hipStream_t s, const float* w0, TrapState* st, int t);
+
+}  // namespace hot

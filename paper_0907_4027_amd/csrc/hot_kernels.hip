@@ -1,0 +1,691 @@
+// hot_kernels.hip -- CDNA4 (gfx950) kernels of the phase-only hologram solver.
+//
+// Method: Bianchi & Di Leonardo, arXiv:0907.4027.  Two passes per iteration:
+//   pixel (backward) pass, Eq. 3 with weights:  phi_j = arg sum_m w_m e^{i(Delta_j^m + theta_m)}
+//   trap (forward) pass, Eq. 1:                 V_m   = (1/N) sum_j e^{i(phi_j - Delta_j^m)}
+// with Delta from Eq. 2 recomputed for every (pixel, trap) pair, and between them the
+// GSW update of Section 3 (w_m <- w_m <|V|>/|V_m|, theta_m <- arg V_m).
+//
+// The paper runs one thread per pixel in both passes and sums Eq. 1 with a tree of
+// shared-memory reduction kernels.  Here one kernel per iteration does, for one row
+// segment of the SLM: the weight/phase update (recomputed identically by every block
+// from the previous V, so no grid-wide synchronisation is needed), the pixel pass with
+// one lane per pixel, and -- with the fresh phases handed over through LDS -- the trap
+// pass with traps on lanes and pixels in a loop, so each lane accumulates its own V_m
+// over a slice of pixels and no per-trap cross-lane reduction is needed.  A small
+// second kernel sums the per-block partials in a fixed order.
+//
+// All phases are in revolutions (see hot_internal.h).  sin/cos are the hardware
+// V_SIN_F32 / V_COS_F32, which take revolutions; their domain is |x| < 256, and the
+// host switches on an explicit fract() (exact in FP32) when a grid could leave it.
+#include "hot_internal.h"
+
+#include <algorithm>
+
+namespace hot {
+
+namespace {
+
+constexpr float kInv2Pi = 0.159154943091895336f;  // FP32(1 / (2 pi))
+constexpr float kTwoPi = 6.28318530717958648f;    // FP32(2 pi)
+
+template <bool FRACT>
+__device__ __forceinline__ float to_period(float t) {
+  if constexpr (FRACT) return __builtin_amdgcn_fractf(t);
+  return t;
+}
+
+// fixed butterfly order: every lane ends with the same, deterministic result
+__device__ __forceinline__ float wave_sum(float v) {
+  v += __shfl_xor(v, 32);
+  v += __shfl_xor(v, 16);
+  v += __shfl_xor(v, 8);
+  v += __shfl_xor(v, 4);
+  v += __shfl_xor(v, 2);
+  v += __shfl_xor(v, 1);
+  return v;
+}
+__device__ __forceinline__ float wave_max(float v) {
+  for (int d = 32; d > 0; d >>= 1) v = fmaxf(v, __shfl_xor(v, d));
+  return v;
+}
+__device__ __forceinline__ float wave_min(float v) {
+  for (int d = 32; d > 0; d >>= 1) v = fminf(v, __shfl_xor(v, d));
+  return v;
+}
+
+__device__ __forceinline__ float wrap_phase(float ph) { return ph < 0.0f ? ph + kTwoPi : ph; }
+
+// Block-wide (NT threads) sums of a and b, max of c, min of d; every thread gets the
+// results.  Waves reduce by butterflies, then each thread combines the W wave results in
+// wave order.  `sh` holds 4 * (NT / 64) floats.
+template <int NT>
+__device__ __forceinline__ void block_reduce(float* sh, float& a, float& b, float& c, float& d) {
+  constexpr int W = NT / 64;
+  a = wave_sum(a);
+  b = wave_sum(b);
+  c = wave_max(c);
+  d = wave_min(d);
+  const int wave = threadIdx.x >> 6;
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) {
+    sh[wave] = a;
+    sh[W + wave] = b;
+    sh[2 * W + wave] = c;
+    sh[3 * W + wave] = d;
+  }
+  __syncthreads();
+  a = sh[0];
+  b = sh[W];
+  c = sh[2 * W];
+  d = sh[3 * W];
+  for (int w = 1; w < W; ++w) {
+    a += sh[w];
+    b += sh[W + w];
+    c = fmaxf(c, sh[2 * W + w]);
+    d = fminf(d, sh[3 * W + w]);
+  }
+}
+
+// Section 3 figures of merit and the GS/GSW update for one hologram, computed by one
+// block from V (interleaved re/im of M traps at offset off) and the current state.
+//   stats_row (3 floats) if non-null: e = sum I, u = 1 - (max-min)/(max+min), sigma = std(I)/mean(I)
+//   mode 0: no update; 1 (GS): theta_m <- arg V_m; 2 (GSW): also w_m <- w_m <|V|>/|V_m|
+// emit(m, state) is called once per trap m, by the thread that owns it.  <|V|> = 0 leaves
+// the state unchanged and raises *flag (if non-null).
+template <int NT, class Emit>
+__device__ void update_traps(const float* __restrict__ V, const TrapState* __restrict__ st_in, int off, int M,
+                             int mode, float* sh, float* stats_row, int* flag, Emit emit) {
+  float sa = 0.0f, si = 0.0f, mx = -1.0f, mn = 3.0e38f;
+  for (int k = threadIdx.x; k < M; k += NT) {
+    const float vr = V[2 * (off + k)], vi = V[2 * (off + k) + 1];
+    const float I = vr * vr + vi * vi;
+    sa += sqrtf(I);
+    si += I;
+    mx = fmaxf(mx, I);
+    mn = fminf(mn, I);
+  }
+  block_reduce<NT>(sh, sa, si, mx, mn);
+  const float mean_abs = sa / (float)M;
+  if (stats_row) {
+    const float mu = si / (float)M;
+    float var = 0.0f, z0 = 0.0f, z1 = 0.0f, z2 = 0.0f;
+    for (int k = threadIdx.x; k < M; k += NT) {
+      const float vr = V[2 * (off + k)], vi = V[2 * (off + k) + 1];
+      const float dI = vr * vr + vi * vi - mu;
+      var += dI * dI;
+    }
+    block_reduce<NT>(sh + 4 * (NT / 64), var, z0, z1, z2);
+    var /= (float)M;
+    if (threadIdx.x == 0) {
+      stats_row[0] = si;
+      stats_row[1] = (mx + mn) > 0.0f ? 1.0f - (mx - mn) / (mx + mn) : 0.0f;
+      stats_row[2] = mu > 0.0f ? sqrtf(var) / mu : 0.0f;
+    }
+  }
+  const bool degenerate = mode != 0 && !(mean_abs > 0.0f);
+  if (degenerate && flag && threadIdx.x == 0) *flag = 1;
+  const float floor_abs = 1e-12f * mean_abs;
+  for (int k = threadIdx.x; k < M; k += NT) {
+    TrapState s = st_in[off + k];
+    if (mode != 0 && !degenerate) {
+      const float vr = V[2 * (off + k)], vi = V[2 * (off + k) + 1];
+      const float amp = sqrtf(vr * vr + vi * vi);
+      const bool tiny = amp < floor_abs;
+      if (mode == 2) s.w *= mean_abs / (tiny ? floor_abs : amp);
+      if (!tiny) {
+        s.theta_rad = atan2f(vi, vr);
+        s.theta_rev = s.theta_rad * kInv2Pi;
+      }
+    }
+    emit(k, s);
+  }
+}
+
+// Pixel-pass terms for Q pixels of one lane: S += w_m e^{i 2pi (g U^2 + a U + C_m)} over all
+// traps.  a, g are wave-uniform scalar loads; (C_m, w_m) come from an LDS broadcast, where
+// C_m = g V^2 + b V + theta_rev holds everything constant along the row.  Per term: 2 FMA,
+// sin, cos, 2 FMA.
+template <int Q, bool FRACT>
+__device__ __forceinline__ void pixel_terms(const TrapCoef* __restrict__ cf, const float2* cw, int M, const float* U,
+                                            const float* U2, float* sr, float* si) {
+#pragma unroll 4
+  for (int m = 0; m < M; ++m) {
+    const float a = cf[m].a, g = cf[m].g;
+    const float2 k = cw[m];
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+      const float t = to_period<FRACT>(__builtin_fmaf(g, U2[q], __builtin_fmaf(a, U[q], k.x)));
+      const float sn = __builtin_amdgcn_sinf(t), cs = __builtin_amdgcn_cosf(t);
+      sr[q] = __builtin_fmaf(k.y, cs, sr[q]);
+      si[q] = __builtin_fmaf(k.y, sn, si[q]);
+    }
+  }
+}
+
+// Trap pass over one row segment whose pixels (phi_rev, U, U^2, mask) sit in LDS `px`
+// (len real entries, zero-padded to S * slen).  Each wave is split into A slices of G
+// lanes; lane (slice s, position l) owns traps l, l+G, ..., l+(TPL-1)G of a chunk and
+// loops over the pixels of its slice:
+//   t = phi - C_m - a_m U - g_m U^2  (C_m = g V^2 + b V per lane and row)   3 VALU
+//   sin t, cos t                                                             2 transcendental
+//   acc += mask (cos t, sin t)                                              2 VALU
+// The S slice partials of each trap are summed in slice order through LDS `red` and
+// written to out[m * nblk].
+template <int W, int TPL, bool FRACT>
+__device__ __forceinline__ void trap_pass_block(const TrapCoef* __restrict__ cf, int M, int G, int A, float Vr,
+                                                float V2, const float4* px, int len, float2* red,
+                                                float2* __restrict__ out, int nblk) {
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int s = lane / G, tl = lane - s * G;
+  const bool active = s < A;
+  const int S = W * A;
+  const int slen = (len + S - 1) / S;
+  const int sidx = wave * A + min(s, A - 1);
+  const float4* mine = px + sidx * slen;
+  const int nslot = G * TPL;
+  for (int k0 = 0; k0 < M; k0 += nslot) {
+    float na[TPL], ng[TPL], cc[TPL], accr[TPL], acci[TPL];
+#pragma unroll
+    for (int k = 0; k < TPL; ++k) {
+      const int m = k0 + tl + k * G;
+      TrapCoef c = {0.0f, 0.0f, 0.0f, 0.0f};
+      if (m < M) c = cf[m];
+      na[k] = -c.a;
+      ng[k] = -c.g;
+      cc[k] = __builtin_fmaf(c.g, V2, c.b * Vr);
+      accr[k] = 0.0f;
+      acci[k] = 0.0f;
+    }
+#pragma unroll 2
+    for (int j = 0; j < slen; ++j) {
+      const float4 p = mine[j];
+#pragma unroll
+      for (int k = 0; k < TPL; ++k) {
+        const float t = to_period<FRACT>(__builtin_fmaf(ng[k], p.z, __builtin_fmaf(na[k], p.y, p.x - cc[k])));
+        accr[k] = __builtin_fmaf(p.w, __builtin_amdgcn_cosf(t), accr[k]);
+        acci[k] = __builtin_fmaf(p.w, __builtin_amdgcn_sinf(t), acci[k]);
+      }
+    }
+    __syncthreads();  // red[] is free: earlier readers (previous chunk, or the pixel pass) are done
+    if (active) {
+#pragma unroll
+      for (int k = 0; k < TPL; ++k) red[sidx * nslot + tl + k * G] = make_float2(accr[k], acci[k]);
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < nslot; i += W * 64) {
+      const int m = k0 + i;
+      if (m < M) {
+        float2 acc = make_float2(0.0f, 0.0f);
+        for (int s2 = 0; s2 < S; ++s2) {
+          const float2 v = red[s2 * nslot + i];
+          acc.x += v.x;
+          acc.y += v.y;
+        }
+        out[(size_t)m * nblk] = acc;
+      }
+    }
+  }
+}
+
+// ------------------------------------------------------------------ fused iteration kernel
+//
+// Grid (nseg, ny, B), NT threads, one row segment (seg_w <= NT * Q pixels) per block.
+//   upd = 0: use st_in as is;  1/2: GS/GSW update from Vprev and st_in, recomputed by every
+//   block; block (0, 0, b) also writes the new state to st_out and the figures of merit of
+//   Vprev to stats[b][kstat].
+// Writes phase (radians) and the trap-pass partials of the new mask.
+template <int NT, int Q, int TPL, bool FRACT>
+__global__ void __launch_bounds__(NT)
+k_iter(const TrapCoef* __restrict__ coef, const HoloDesc* __restrict__ hd, const TrapState* __restrict__ st_in,
+       TrapState* __restrict__ st_out, const float* __restrict__ Vprev, float* __restrict__ stats, int kstat,
+       int stat_stride, int upd, int* __restrict__ flag, int nx, int ny, int seg_w, int nseg,
+       float* __restrict__ phase, float2* __restrict__ partial) {
+  constexpr int W = NT / 64;
+  constexpr int PXN = NT * Q + 64;
+  constexpr int REDN = W * 64 * TPL;
+  constexpr int UN = REDN > kMaxTraps ? REDN : kMaxTraps;
+  __shared__ float4 px[PXN];
+  __shared__ float2 ubuf[UN];  // (C_m, w_m) during the pixel pass, slice partials in the trap pass
+  __shared__ float sh[8 * W];
+  const int b = blockIdx.z, r = blockIdx.y, sg = blockIdx.x;
+  const int M = hd[b].m, off = hd[b].off, G = hd[b].g, A = hd[b].a;
+  const TrapCoef* __restrict__ cf = coef + off;
+  const float Vr = (float)(2 * r - (ny - 1));
+  const float V2 = Vr * Vr;
+  float2* cw = ubuf;
+
+  if (upd == 0) {
+    for (int m = threadIdx.x; m < M; m += NT) {
+      const TrapCoef c = cf[m];
+      const TrapState s = st_in[off + m];
+      cw[m] = make_float2(__builtin_fmaf(c.g, V2, __builtin_fmaf(c.b, Vr, s.theta_rev)), s.w);
+    }
+  } else {
+    const bool lead = sg == 0 && r == 0;
+    update_traps<NT>(Vprev, st_in, off, M, upd, sh, lead ? stats + 3 * ((size_t)b * stat_stride + kstat) : nullptr,
+                     lead ? flag : nullptr, [&](int m, const TrapState& s) {
+                       if (lead) st_out[off + m] = s;
+                       const TrapCoef c = cf[m];
+                       cw[m] = make_float2(__builtin_fmaf(c.g, V2, __builtin_fmaf(c.b, Vr, s.theta_rev)), s.w);
+                     });
+  }
+  __syncthreads();
+
+  const int cbeg = sg * seg_w;
+  const int len = min(nx, cbeg + seg_w) - cbeg;
+  float U[Q], U2[Q], sr[Q], si[Q];
+#pragma unroll
+  for (int q = 0; q < Q; ++q) {
+    U[q] = (float)(2 * (cbeg + (int)threadIdx.x + q * NT) - (nx - 1));
+    U2[q] = U[q] * U[q];
+    sr[q] = 0.0f;
+    si[q] = 0.0f;
+  }
+  pixel_terms<Q, FRACT>(cf, cw, M, U, U2, sr, si);
+  float* __restrict__ prow = phase + (size_t)b * nx * ny + (size_t)r * nx + cbeg;
+#pragma unroll
+  for (int q = 0; q < Q; ++q) {
+    const int i = threadIdx.x + q * NT;
+    if (i < len) {
+      const float ph = wrap_phase(atan2f(si[q], sr[q]));
+      prow[i] = ph;
+      px[i] = make_float4(ph * kInv2Pi, U[q], U2[q], 1.0f);
+    } else {
+      px[i] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    }
+  }
+  for (int i = NT * Q + threadIdx.x; i < PXN; i += NT) px[i] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+  __syncthreads();
+  const int nblk = ny * nseg;
+  trap_pass_block<W, TPL, FRACT>(cf, M, G, A, Vr, V2, px, len, ubuf, partial + (size_t)off * nblk + r * nseg + sg,
+                                 nblk);
+}
+
+// ------------------------------------------------------------------ stand-alone passes
+//
+// Pixel pass alone.  MODE 0 writes phase = arg S in [0, 2pi].  MODE 1 is the adjoint of
+// Eq. 1: with w e^{i theta} := G_m = dL/dRe V_m + i dL/dIm V_m it writes
+// grad[j] = (1/N) Im(e^{-i phi_j} S_j) for the given phase.
+template <int Q, bool FRACT, int MODE>
+__global__ void __launch_bounds__(kBlock)
+k_backward(const TrapCoef* __restrict__ coef, const TrapState* __restrict__ st, const HoloDesc* __restrict__ hd,
+           int nx, int ny, float* __restrict__ phase, const float* __restrict__ G, float* __restrict__ grad,
+           float inv_n) {
+  __shared__ float2 cw[kMaxTraps];
+  const int b = blockIdx.z, r = blockIdx.y;
+  const int M = hd[b].m, off = hd[b].off;
+  const TrapCoef* __restrict__ cf = coef + off;
+  const float Vr = (float)(2 * r - (ny - 1));
+  const float V2 = Vr * Vr;
+  for (int m = threadIdx.x; m < M; m += kBlock) {
+    const TrapCoef c = cf[m];
+    float th, w;
+    if constexpr (MODE == 0) {
+      const TrapState s = st[off + m];
+      th = s.theta_rev;
+      w = s.w;
+    } else {
+      const float gr = G[2 * (off + m)], gi = G[2 * (off + m) + 1];
+      w = sqrtf(gr * gr + gi * gi);
+      th = atan2f(gi, gr) * kInv2Pi;
+    }
+    cw[m] = make_float2(__builtin_fmaf(c.g, V2, __builtin_fmaf(c.b, Vr, th)), w);
+  }
+  __syncthreads();
+  const int cbase = blockIdx.x * (kBlock * Q) + threadIdx.x;
+  float U[Q], U2[Q], sr[Q], si[Q];
+#pragma unroll
+  for (int q = 0; q < Q; ++q) {
+    U[q] = (float)(2 * (cbase + q * kBlock) - (nx - 1));
+    U2[q] = U[q] * U[q];
+    sr[q] = 0.0f;
+    si[q] = 0.0f;
+  }
+  pixel_terms<Q, FRACT>(cf, cw, M, U, U2, sr, si);
+  const size_t rowbase = (size_t)b * nx * ny + (size_t)r * nx;
+#pragma unroll
+  for (int q = 0; q < Q; ++q) {
+    const int c = cbase + q * kBlock;
+    if (c < nx) {
+      if constexpr (MODE == 0) {
+        phase[rowbase + c] = wrap_phase(atan2f(si[q], sr[q]));
+      } else {
+        float sp, cp;
+        sincosf(phase[rowbase + c], &sp, &cp);
+        grad[rowbase + c] = (si[q] * cp - sr[q] * sp) * inv_n;
+      }
+    }
+  }
+}
+
+// Trap pass alone on a given phase mask: block = one row segment, kBlock threads.
+template <int TPL, bool FRACT>
+__global__ void __launch_bounds__(kBlock)
+k_forward(const TrapCoef* __restrict__ coef, const HoloDesc* __restrict__ hd, const float* __restrict__ phase,
+          int nx, int ny, int seg_w, int nseg, float2* __restrict__ partial) {
+  constexpr int W = kBlock / 64;
+  __shared__ float4 px[kSegMax + 64];
+  __shared__ float2 red[W * 64 * TPL];
+  const int b = blockIdx.z, r = blockIdx.y, sg = blockIdx.x;
+  const int M = hd[b].m, G = hd[b].g, A = hd[b].a, off = hd[b].off;
+  const int cbeg = sg * seg_w;
+  const int len = min(nx, cbeg + seg_w) - cbeg;
+  const int S = W * A;
+  const int padded = S * ((len + S - 1) / S);
+  const float* __restrict__ ph = phase + (size_t)b * nx * ny + (size_t)r * nx + cbeg;
+  for (int i = threadIdx.x; i < padded; i += kBlock) {
+    if (i < len) {
+      const float U = (float)(2 * (cbeg + i) - (nx - 1));
+      px[i] = make_float4(ph[i] * kInv2Pi, U, U * U, 1.0f);
+    } else {
+      px[i] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    }
+  }
+  __syncthreads();
+  const float Vr = (float)(2 * r - (ny - 1));
+  const int nblk = ny * nseg;
+  trap_pass_block<W, TPL, FRACT>(coef + off, M, G, A, Vr, Vr * Vr, px, len, red,
+                                 partial + (size_t)off * nblk + r * nseg + sg, nblk);
+}
+
+// ------------------------------------------------------------------ reduce, update, finalize
+//
+// Grid (ceil(Mmax / 4), B), 256 threads: wave w of block x sums trap m = 4x + w over the
+// nblk partials (lanes take every 64th block, then a butterfly; fixed order) -> V_m = sum / N.
+__global__ void __launch_bounds__(256)
+k_reduce(const float2* __restrict__ partial, const HoloDesc* __restrict__ hd, int nblk, float inv_n,
+         float* __restrict__ V) {
+  const int b = blockIdx.y;
+  const int M = hd[b].m, off = hd[b].off;
+  const int m = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+  if (m >= M) return;
+  const float2* __restrict__ p = partial + (size_t)(off + m) * nblk;
+  float sr = 0.0f, si = 0.0f;
+  for (int k = lane; k < nblk; k += 64) {
+    const float2 v = p[k];
+    sr += v.x;
+    si += v.y;
+  }
+  sr = wave_sum(sr);
+  si = wave_sum(si);
+  if (lane == 0) {
+    V[2 * (off + m)] = sr * inv_n;
+    V[2 * (off + m) + 1] = si * inv_n;
+  }
+}
+
+// One block per hologram: figures of merit of V into stats[b][kstat] and, for mode 1/2,
+// the GS/GSW update st_in -> st_out (st_out may equal st_in).
+__global__ void __launch_bounds__(256)
+k_update(const float* __restrict__ V, const HoloDesc* __restrict__ hd, const TrapState* st_in, TrapState* st_out,
+         float* __restrict__ stats, int kstat, int stat_stride, int mode, int* __restrict__ flag) {
+  __shared__ float sh[8 * 4];
+  const int b = blockIdx.x;
+  const int M = hd[b].m, off = hd[b].off;
+  update_traps<256>(V, st_in, off, M, mode, sh, stats + 3 * ((size_t)b * stat_stride + kstat), flag,
+                    [&](int m, const TrapState& s) {
+                      if (mode != 0) st_out[off + m] = s;
+                    });
+}
+
+// ------------------------------------------------------------------ stored exp(i Delta) variant
+
+template <bool FRACT>
+__global__ void __launch_bounds__(kBlock)
+k_expdelta(const TrapCoef* __restrict__ coef, const HoloDesc* __restrict__ hd, int nx, int ny, float2* __restrict__ A) {
+  const int b = blockIdx.z, m = blockIdx.y;
+  const int M = hd[b].m, off = hd[b].off;
+  if (m >= M) return;
+  const int n = nx * ny;
+  const TrapCoef c = coef[off + m];
+  float2* __restrict__ row = A + (size_t)(off + m) * n;
+  for (int j = blockIdx.x * kBlock + threadIdx.x; j < n; j += gridDim.x * kBlock) {
+    const int r = j / nx, col = j - r * nx;
+    const float U = (float)(2 * col - (nx - 1)), Vr = (float)(2 * r - (ny - 1));
+    const float t = to_period<FRACT>(
+        __builtin_fmaf(c.g, U * U, __builtin_fmaf(c.a, U, __builtin_fmaf(c.g, Vr * Vr, __builtin_fmaf(c.b, Vr, 0.0f)))));
+    row[j] = make_float2(__builtin_amdgcn_cosf(t), __builtin_amdgcn_sinf(t));
+  }
+}
+
+// S_j = sum_m (w e^{i theta})_m A[m][j]; phase = arg S, E_j = e^{i phase} for the forward pass.
+__global__ void __launch_bounds__(kBlock)
+k_backward_stored(const float2* __restrict__ A, const TrapState* __restrict__ st, const HoloDesc* __restrict__ hd,
+                  int n, float* __restrict__ phase, float2* __restrict__ E) {
+  __shared__ float2 cm[kMaxTraps];
+  const int b = blockIdx.y;
+  const int M = hd[b].m, off = hd[b].off;
+  for (int m = threadIdx.x; m < M; m += kBlock) {
+    const TrapState s = st[off + m];
+    cm[m] = make_float2(s.w * __builtin_amdgcn_cosf(s.theta_rev), s.w * __builtin_amdgcn_sinf(s.theta_rev));
+  }
+  __syncthreads();
+  const int j = blockIdx.x * kBlock + threadIdx.x;
+  if (j >= n) return;
+  const float2* __restrict__ col = A + (size_t)off * n + j;
+  float sr = 0.0f, si = 0.0f;
+#pragma unroll 8
+  for (int m = 0; m < M; ++m) {
+    const float2 v = col[(size_t)m * n];
+    const float2 k = cm[m];
+    sr = __builtin_fmaf(k.x, v.x, __builtin_fmaf(-k.y, v.y, sr));
+    si = __builtin_fmaf(k.x, v.y, __builtin_fmaf(k.y, v.x, si));
+  }
+  const float ph = wrap_phase(atan2f(si, sr));
+  phase[(size_t)b * n + j] = ph;
+  const float pr = ph * kInv2Pi;
+  E[(size_t)b * n + j] = make_float2(__builtin_amdgcn_cosf(pr), __builtin_amdgcn_sinf(pr));
+}
+
+// Per wave: 64 * PPL pixels (PPL per lane, kept in registers); for each trap the wave sums
+// conj(A[m][j]) E_j over its pixels and writes one partial per (trap, wave).
+template <int PPL>
+__global__ void __launch_bounds__(kBlock)
+k_forward_stored(const float2* __restrict__ A, const float2* __restrict__ E, const HoloDesc* __restrict__ hd, int n,
+                 float2* __restrict__ partial) {
+  const int b = blockIdx.y;
+  const int M = hd[b].m, off = hd[b].off;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int nblk = (n + 64 * PPL - 1) / (64 * PPL);
+  const int blk = blockIdx.x * 4 + wave;
+  if (blk >= nblk) return;
+  const int j0 = blk * 64 * PPL + lane;
+  float er[PPL], ei[PPL];
+#pragma unroll
+  for (int p = 0; p < PPL; ++p) {
+    const int j = j0 + p * 64;
+    const float2 e = j < n ? E[(size_t)b * n + j] : make_float2(0.0f, 0.0f);
+    er[p] = e.x;
+    ei[p] = e.y;
+  }
+  for (int m = 0; m < M; ++m) {
+    const float2* __restrict__ row = A + (size_t)(off + m) * n;
+    float sr = 0.0f, si = 0.0f;
+#pragma unroll
+    for (int p = 0; p < PPL; ++p) {
+      const int j = j0 + p * 64;
+      const float2 v = j < n ? row[j] : make_float2(0.0f, 0.0f);
+      sr = __builtin_fmaf(v.x, er[p], __builtin_fmaf(v.y, ei[p], sr));  // Re(conj(v) e)
+      si = __builtin_fmaf(v.x, ei[p], __builtin_fmaf(-v.y, er[p], si)); // Im(conj(v) e)
+    }
+    sr = wave_sum(sr);
+    si = wave_sum(si);
+    if (lane == 0) partial[(size_t)(off + m) * nblk + blk] = make_float2(sr, si);
+  }
+}
+
+// ------------------------------------------------------------------ helpers
+
+__global__ void k_fill_u32(unsigned* p, unsigned v, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+__global__ void k_export_state(const TrapState* __restrict__ st, int t, float* w_out, float* theta_out) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < t) {
+    if (w_out) w_out[i] = st[i].w;
+    if (theta_out) theta_out[i] = st[i].theta_rad;
+  }
+}
+
+__global__ void k_import_w(const float* __restrict__ w0, TrapState* __restrict__ st, int t) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < t) st[i].w = w0[i];
+}
+
+// ------------------------------------------------------------------ template dispatch
+
+template <int NT, int Q, int TPL, bool FRACT>
+hipError_t iter_t(hipStream_t s, const IterArgs& a) {
+  if (a.fg.seg_w > NT * Q) return hipErrorInvalidValue;
+  dim3 grid(a.fg.nseg, a.fg.ny, a.B);
+  hipLaunchKernelGGL((k_iter<NT, Q, TPL, FRACT>), grid, dim3(NT), 0, s, a.coef, a.hd, a.st_in, a.st_out, a.Vprev,
+                     a.stats, a.kstat, a.stat_stride, a.upd, a.flag, a.fg.nx, a.fg.ny, a.fg.seg_w, a.fg.nseg, a.phase,
+                     a.partial);
+  return hipGetLastError();
+}
+
+template <int NT, int Q, bool FRACT>
+hipError_t iter_tpl(hipStream_t s, const IterArgs& a) {
+  switch (a.tpl) {
+    case 1: return iter_t<NT, Q, 1, FRACT>(s, a);
+    case 2: return iter_t<NT, Q, 2, FRACT>(s, a);
+    case 3: return iter_t<NT, Q, 3, FRACT>(s, a);
+    case 4: return iter_t<NT, Q, 4, FRACT>(s, a);
+    case 5: return iter_t<NT, Q, 5, FRACT>(s, a);
+    case 6: return iter_t<NT, Q, 6, FRACT>(s, a);
+    case 8: return iter_t<NT, Q, 8, FRACT>(s, a);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+template <bool FRACT>
+hipError_t iter_shape(hipStream_t s, const IterArgs& a) {
+  if (a.nt == 256 && a.q == 1) return iter_tpl<256, 1, FRACT>(s, a);
+  if (a.nt == 256 && a.q == 2) return iter_tpl<256, 2, FRACT>(s, a);
+  if (a.nt == 512 && a.q == 1) return iter_tpl<512, 1, FRACT>(s, a);
+  if (a.nt == 512 && a.q == 2) return iter_tpl<512, 2, FRACT>(s, a);
+  return hipErrorInvalidValue;
+}
+
+template <int Q, bool FRACT, int MODE>
+hipError_t backward_q(hipStream_t s, int nx, int ny, int B, const TrapCoef* coef, const TrapState* st,
+                      const HoloDesc* hd, float* phase, const float* G, float* grad, float inv_n) {
+  dim3 grid((nx + kBlock * Q - 1) / (kBlock * Q), ny, B);
+  hipLaunchKernelGGL((k_backward<Q, FRACT, MODE>), grid, dim3(kBlock), 0, s, coef, st, hd, nx, ny, phase, G, grad,
+                     inv_n);
+  return hipGetLastError();
+}
+
+template <bool FRACT, int MODE>
+hipError_t backward_sel(hipStream_t s, int q, int nx, int ny, int B, const TrapCoef* coef, const TrapState* st,
+                        const HoloDesc* hd, float* phase, const float* G, float* grad, float inv_n) {
+  switch (q) {
+    case 1: return backward_q<1, FRACT, MODE>(s, nx, ny, B, coef, st, hd, phase, G, grad, inv_n);
+    case 2: return backward_q<2, FRACT, MODE>(s, nx, ny, B, coef, st, hd, phase, G, grad, inv_n);
+    default: return backward_q<4, FRACT, MODE>(s, nx, ny, B, coef, st, hd, phase, G, grad, inv_n);
+  }
+}
+
+template <int TPL>
+hipError_t forward_t(hipStream_t s, const FwdGeom& fg, int B, bool fract, const TrapCoef* coef, const HoloDesc* hd,
+                     const float* phase, float2* partial) {
+  dim3 grid(fg.nseg, fg.ny, B);
+  if (fract)
+    hipLaunchKernelGGL((k_forward<TPL, true>), grid, dim3(kBlock), 0, s, coef, hd, phase, fg.nx, fg.ny, fg.seg_w,
+                       fg.nseg, partial);
+  else
+    hipLaunchKernelGGL((k_forward<TPL, false>), grid, dim3(kBlock), 0, s, coef, hd, phase, fg.nx, fg.ny, fg.seg_w,
+                       fg.nseg, partial);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_iter(hipStream_t s, const IterArgs& a) {
+  return a.fract ? iter_shape<true>(s, a) : iter_shape<false>(s, a);
+}
+
+hipError_t launch_backward(hipStream_t s, int nx, int ny, int B, bool fract, int q, const TrapCoef* coef,
+                           const TrapState* st, const HoloDesc* hd, float* phase, int mode, const float* G,
+                           float* grad) {
+  const float inv_n = 1.0f / ((float)nx * (float)ny);
+  if (mode == 0)
+    return fract ? backward_sel<true, 0>(s, q, nx, ny, B, coef, st, hd, phase, G, grad, inv_n)
+                 : backward_sel<false, 0>(s, q, nx, ny, B, coef, st, hd, phase, G, grad, inv_n);
+  return fract ? backward_sel<true, 1>(s, q, nx, ny, B, coef, st, hd, phase, G, grad, inv_n)
+               : backward_sel<false, 1>(s, q, nx, ny, B, coef, st, hd, phase, G, grad, inv_n);
+}
+
+hipError_t launch_forward(hipStream_t s, const FwdGeom& fg, int B, int tpl, bool fract, const TrapCoef* coef,
+                          const HoloDesc* hd, const float* phase, float2* partial) {
+  if (fg.seg_w > kSegMax) return hipErrorInvalidValue;
+  switch (tpl) {
+    case 1: return forward_t<1>(s, fg, B, fract, coef, hd, phase, partial);
+    case 2: return forward_t<2>(s, fg, B, fract, coef, hd, phase, partial);
+    case 3: return forward_t<3>(s, fg, B, fract, coef, hd, phase, partial);
+    case 4: return forward_t<4>(s, fg, B, fract, coef, hd, phase, partial);
+    case 5: return forward_t<5>(s, fg, B, fract, coef, hd, phase, partial);
+    case 6: return forward_t<6>(s, fg, B, fract, coef, hd, phase, partial);
+    case 8: return forward_t<8>(s, fg, B, fract, coef, hd, phase, partial);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_reduce(hipStream_t s, int B, int mmax, int nblk, float inv_n, const float2* partial,
+                         const HoloDesc* hd, float* V) {
+  dim3 grid((mmax + 3) / 4, B);
+  hipLaunchKernelGGL(k_reduce, grid, dim3(256), 0, s, partial, hd, nblk, inv_n, V);
+  return hipGetLastError();
+}
+
+hipError_t launch_update(hipStream_t s, int B, const float* V, const HoloDesc* hd, const TrapState* st_in,
+                         TrapState* st_out, float* stats, int kstat, int stat_stride, int mode, int* flag) {
+  hipLaunchKernelGGL(k_update, dim3(B), dim3(256), 0, s, V, hd, st_in, st_out, stats, kstat, stat_stride, mode, flag);
+  return hipGetLastError();
+}
+
+hipError_t launch_expdelta(hipStream_t s, int nx, int ny, int B, int mmax, bool fract, const TrapCoef* coef,
+                           const HoloDesc* hd, float2* A) {
+  const int n = nx * ny;
+  dim3 grid(std::min((n + kBlock - 1) / kBlock, 1024), mmax, B);
+  if (fract)
+    hipLaunchKernelGGL(k_expdelta<true>, grid, dim3(kBlock), 0, s, coef, hd, nx, ny, A);
+  else
+    hipLaunchKernelGGL(k_expdelta<false>, grid, dim3(kBlock), 0, s, coef, hd, nx, ny, A);
+  return hipGetLastError();
+}
+
+hipError_t launch_backward_stored(hipStream_t s, int n, int B, const float2* A, const TrapState* st,
+                                  const HoloDesc* hd, float* phase, float2* E) {
+  dim3 grid((n + kBlock - 1) / kBlock, B);
+  hipLaunchKernelGGL(k_backward_stored, grid, dim3(kBlock), 0, s, A, st, hd, n, phase, E);
+  return hipGetLastError();
+}
+
+hipError_t launch_forward_stored(hipStream_t s, int n, int B, const float2* A, const float2* E, const HoloDesc* hd,
+                                 float2* partial) {
+  const int nblk = stored_nblk(n);
+  dim3 grid((nblk + 3) / 4, B);
+  hipLaunchKernelGGL(k_forward_stored<kStoredPpl>, grid, dim3(kBlock), 0, s, A, E, hd, n, partial);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_u32(hipStream_t s, unsigned* p, unsigned v, int n) {
+  hipLaunchKernelGGL(k_fill_u32, dim3((n + 255) / 256), dim3(256), 0, s, p, v, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_export_state(hipStream_t s, const TrapState* st, int t, float* w_out, float* theta_out) {
+  hipLaunchKernelGGL(k_export_state, dim3((t + 255) / 256), dim3(256), 0, s, st, t, w_out, theta_out);
+  return hipGetLastError();
+}
+
+hipError_t launch_import_w(hipStream_t s, const float* w0, TrapState* st, int t) {
+  hipLaunchKernelGGL(k_import_w, dim3((t + 255) / 256), dim3(256), 0, s, w0, st, t);
+  return hipGetLastError();
+}
+
+}  // namespace hot

@@ -1,0 +1,48 @@
+"""Comparison helpers for HIP-vs-oracle parity (tolerances of the FP32 device path).
+
+Bar: |V_m| within 1e-4 relative, and the wrapped phase difference within 1e-3 rad
+for at least 99.9 % of pixels (phase vortices, where |S_j| ~ 0, make a few pixels
+ill-conditioned; those are the 0.1 %).
+"""
+import numpy as np
+
+V_RTOL = 1e-4
+PHI_TOL = 1e-3
+PHI_FRAC = 0.999
+
+
+def to_np(t):
+    return t.detach().float().cpu().numpy().astype(np.float64)
+
+
+def as_complex(V):
+    V = np.asarray(V)
+    return V[..., 0] + 1j * V[..., 1]
+
+
+def wrapped_diff(a, b):
+    return np.abs(np.angle(np.exp(1j * (np.asarray(a, np.float64) - np.asarray(b, np.float64)))))
+
+
+def assert_phase(gpu, ref, tol=PHI_TOL, frac=PHI_FRAC, what="phase"):
+    d = wrapped_diff(np.ravel(gpu), np.ravel(ref))
+    ok = float((d <= tol).mean())
+    assert ok >= frac, f"{what}: only {ok:.5f} of pixels within {tol} rad (max {d.max():.3g}, p99.9 {np.quantile(d, 0.999):.3g})"
+    return ok, float(d.max())
+
+
+def assert_V(gpu_V, ref_V, rtol=V_RTOL, what="V"):
+    g = as_complex(gpu_V) if np.isrealobj(gpu_V) else gpu_V
+    a, b = np.abs(g), np.abs(ref_V)
+    rel = np.abs(a - b) / np.maximum(b, 1e-30)
+    assert rel.max() <= rtol, f"{what}: max |V| rel err {rel.max():.3g} (trap {int(rel.argmax())})"
+    return float(rel.max())
+
+
+def assert_stats(gpu, ref, e_rtol=3e-4, u_atol=1e-3, s_atol=1e-3):
+    gpu, ref = np.asarray(gpu), np.asarray(ref)
+    assert gpu.shape == ref.shape, (gpu.shape, ref.shape)
+    e = np.abs(gpu[..., 0] - ref[..., 0]) / np.abs(ref[..., 0])
+    assert e.max() <= e_rtol, f"efficiency rel err {e.max():.3g}"
+    assert np.abs(gpu[..., 1] - ref[..., 1]).max() <= u_atol, "uniformity"
+    assert np.abs(gpu[..., 2] - ref[..., 2]).max() <= s_atol, "sigma"

@@ -1,0 +1,301 @@
+"""HIP path vs the FP64 oracle, through the C ABI (needs an MI355X).
+
+Sizes: full oracle comparisons where the oracle finishes in seconds (the 256^2 x 16
+and 512^2 x 100 workloads, ragged and tiny grids, segmented wide rows), and at the
+1024^2 x 256 workload sampled outputs the oracle computes one by one.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import workloads as W
+from tests.parity import as_complex, assert_phase, assert_stats, assert_V, to_np, wrapped_diff
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(autouse=True)
+def _announce(request):
+    print(f"\n[gpu case] {request.node.nodeid}", file=sys.stderr, flush=True)
+    yield
+
+
+@pytest.fixture(scope="module")
+def ctx(hot):
+    c = hot.Context(0)
+    yield c
+    c.close()
+
+
+def run(ctx, algo, p, iters=None, **kw):
+    iters = p.iters if iters is None else iters
+    if algo == "rs":
+        r = ctx.hot_rs(p.slm, p.xyz, p.theta0, **kw)
+    elif algo == "gs":
+        r = ctx.hot_gs(p.slm, p.xyz, p.theta0, iters, **kw)
+    else:
+        r = ctx.hot_gsw(p.slm, p.xyz, p.theta0, iters, **kw)
+    torch.cuda.synchronize()
+    return r
+
+
+# ------------------------------------------------------------------ full parity, small and ragged grids
+
+CASES = {
+    "c1-256sq-16": lambda: W.c1(),
+    "ragged-300x77-37": lambda: W.random_problem(201, 300, 77, 37),
+    "wide-1500x6-9": lambda: W.random_problem(202, 1500, 6, 9),
+    "tiny-1x1-3": lambda: W.random_problem(203, 1, 1, 3),
+    "tiny-3x5-1": lambda: W.random_problem(204, 3, 5, 1),
+    "odd-129x65-130": lambda: W.random_problem(205, 129, 65, 130),
+}
+
+
+@pytest.mark.parametrize("name", sorted(CASES))
+@pytest.mark.parametrize("algo", ["rs", "gsw"])
+def test_matches_oracle_small(ctx, name, algo):
+    p = CASES[name]()
+    K = 6 if algo == "gsw" else 0
+    g = run(ctx, algo, p, K)
+    o = oracle.solve(algo, p.slm, p.xyz, p.theta0, K)
+    if name == "odd-129x65-130" and algo == "gsw":
+        # 130 traps on 8385 pixels: many near-zero |S_j| (phase vortices), and six GSW
+        # iterations amplify FP32-vs-FP64 differences at them; single passes (rs) meet
+        # the 99.9 % bar on the same grid
+        assert_phase(to_np(g.phase), o["phi"], frac=0.995)
+        assert_V(to_np(g.V), o["V"], rtol=3e-4)
+        assert_stats(g.stats, o["stats"])
+        return
+    if p.slm.n >= 64:
+        assert_phase(to_np(g.phase), o["phi"])
+    else:  # too few pixels for a 0.1 % allowance: every pixel must agree
+        assert_phase(to_np(g.phase), o["phi"], frac=1.0)
+    assert_V(to_np(g.V), o["V"])
+    assert_stats(g.stats, o["stats"])
+
+
+def test_gsw_256sq_4x4_grid_30_iterations(ctx):
+    p = W.c1()
+    g = run(ctx, "gsw", p, state=True)
+    o = oracle.solve("gsw", p.slm, p.xyz, p.theta0, p.iters)
+    assert_phase(to_np(g.phase), o["phi"])
+    assert_V(to_np(g.V), o["V"])
+    assert_stats(g.stats, o["stats"])
+    w = to_np(g.w)
+    np.testing.assert_allclose(w / w.mean(), o["w"] / o["w"].mean(), rtol=1e-3)
+    assert np.max(wrapped_diff(to_np(g.theta), o["theta"])) < 1e-3
+    assert g.stats[-1, 1] > 0.99  # Section 3: almost perfectly uniform after a few tens of iterations
+
+
+@pytest.mark.parametrize("algo", ["rs", "gs", "gsw"])
+def test_512sq_100_traps_50_iterations(ctx, algo):
+    p = W.c2()
+    g = run(ctx, algo, p)
+    o = oracle.solve(algo, p.slm, p.xyz, p.theta0, p.iters)
+    assert_phase(to_np(g.phase), o["phi"])
+    assert_V(to_np(g.V), o["V"])
+    assert_stats(g.stats, o["stats"])
+
+
+# ------------------------------------------------------------------ full size, sampled
+
+def test_1024sq_256_traps_sampled(ctx):
+    """40 GSW iterations at 1024^2 x 256: the final trap pass is checked in full (oracle Eq. 1 on the
+    GPU mask), the final pixel pass on 4096 sampled pixels (oracle Eq. 3 with the GPU's w, theta),
+    and a 3-iteration trajectory in full."""
+    p = W.c3()
+    g = run(ctx, "gsw", p, state=True)
+    phi = to_np(g.phase).ravel()
+    assert_V(to_np(g.V), oracle.forward(p.slm, p.xyz, phi), what="trap pass at K=40")
+    idx = np.random.default_rng(7).choice(p.slm.n, 4096, replace=False)
+    ref = oracle.backward(p.slm, p.xyz, to_np(g.w), to_np(g.theta).astype(np.float64), idx=idx)
+    assert_phase(phi[idx], ref, frac=0.998, what="pixel pass at K=40")
+    assert g.stats[-1, 1] > 0.9
+    g3 = run(ctx, "gsw", p, 3)
+    o3 = oracle.solve("gsw", p.slm, p.xyz, p.theta0, 3)
+    assert_phase(to_np(g3.phase), o3["phi"])
+    assert_V(to_np(g3.V), o3["V"])
+    assert_stats(g3.stats, o3["stats"])
+
+
+# ------------------------------------------------------------------ single passes, batches, adjoint
+
+def test_forward_V_batched_uneven(ctx):
+    probs = [W.random_problem(300 + i, 200, 120, m) for i, m in enumerate((5, 64, 131))]
+    slm = probs[0].slm
+    rng = np.random.default_rng(310)
+    phis = rng.uniform(0, 2 * math.pi, (3, slm.n))
+    counts = [p.m for p in probs]
+    xyz = np.concatenate([p.xyz for p in probs])
+    phase = torch.tensor(phis.reshape(3, slm.ny, slm.nx), dtype=torch.float32, device="cuda")
+    V = to_np(ctx.hot_forward_V(slm, counts, xyz, phase))
+    torch.cuda.synchronize()
+    o = 0
+    for b, p in enumerate(probs):
+        # the oracle sees the same FP32-rounded mask the GPU saw
+        ref = oracle.forward(slm, p.xyz, phis[b].astype(np.float32).astype(np.float64))
+        assert_V(V[o:o + p.m], ref, what=f"hologram {b}")
+        np.testing.assert_allclose(as_complex(V[o:o + p.m]), ref, atol=2e-6)
+        o += p.m
+
+
+@pytest.mark.parametrize("case", ["fd-64sq-4", "512sq-64"])
+def test_adjoint_matches_oracle(ctx, case):
+    if case == "fd-64sq-4":
+        p, phi = W.c5_fd_case()
+    else:
+        p = W.random_problem(320, 512, 512, 64)
+        phi = np.random.default_rng(321).uniform(0, 2 * math.pi, p.slm.n)
+    phi = phi.astype(np.float32).astype(np.float64)
+    G = np.random.default_rng(322).normal(size=p.m) + 1j * np.random.default_rng(323).normal(size=p.m)
+    Gt = torch.tensor(np.stack([G.real, G.imag], -1), dtype=torch.float32, device="cuda")
+    phase = torch.tensor(phi.reshape(1, p.slm.ny, p.slm.nx), dtype=torch.float32, device="cuda")
+    g = to_np(ctx.hot_adjoint(p.slm, [p.m], p.xyz, phase, Gt)).ravel()
+    ref = oracle.adjoint(p.slm, p.xyz, phi, G.astype(np.complex64).astype(np.complex128))
+    rel = np.linalg.norm(g - ref) / np.linalg.norm(ref)
+    assert rel <= 1e-4, rel
+
+
+def test_autograd_gradient_matches_oracle(hot, ctx):
+    p, phi = W.c5_fd_case()
+    phi = phi.astype(np.float32).astype(np.float64)
+    phase = torch.tensor(phi.reshape(1, p.slm.ny, p.slm.nx), dtype=torch.float32, device="cuda",
+                         requires_grad=True)
+    V = hot.TrapField.apply(phase, ctx, p.slm, [p.m], p.xyz)
+    L = hot.trap_intensity_loss(V, [p.m])
+    L.backward()
+    Lo, Vo, go = oracle.loss_grad(p.slm, p.xyz, phi)
+    assert abs(L.item() - Lo) <= 1e-4 * abs(Lo)
+    g = to_np(phase.grad).ravel()
+    rel = np.linalg.norm(g - go) / np.linalg.norm(go)
+    assert rel <= 1e-4, rel
+
+
+def test_batched_equals_plain_and_oracle(ctx):
+    bt = W.c4(8)
+    bt.iters = 10
+    r = ctx.hot_gsw_batched(bt.slm, bt.counts, bt.xyz, bt.theta0, bt.iters)
+    torch.cuda.synchronize()
+    ph, V, st = to_np(r.phase), to_np(r.V), r.stats
+    o = bt.offsets()
+    for b in range(bt.b):
+        p = bt.problem(b)
+        g = run(ctx, "gsw", p, bt.iters)
+        assert_phase(ph[b], to_np(g.phase), what=f"batched vs plain {b}")
+        assert_V(V[o[b]:o[b + 1]], as_complex(to_np(g.V)), what=f"batched vs plain {b}")
+        assert_stats(st[b], g.stats)
+        if b < 2:
+            ref = oracle.solve("gsw", p.slm, p.xyz, p.theta0, bt.iters)
+            assert_phase(ph[b], ref["phi"])
+            assert_V(V[o[b]:o[b + 1]], ref["V"])
+
+
+# ------------------------------------------------------------------ stored exp(i Delta) variant
+
+@pytest.mark.parametrize("algo", ["rs", "gsw"])
+def test_stored_variant_matches_oracle(hot, algo):
+    p = W.random_problem(330, 256, 192, 40)
+    with hot.Context(0) as c:
+        c.set_variant("stored")
+        g = run(c, algo, p, 8)
+    o = oracle.solve(algo, p.slm, p.xyz, p.theta0, 8)
+    assert_phase(to_np(g.phase), o["phi"])
+    assert_V(to_np(g.V), o["V"])
+    assert_stats(g.stats, o["stats"])
+
+
+# ------------------------------------------------------------------ invariants, determinism, edges
+
+def test_single_trap_closed_form(ctx):
+    p = W.random_problem(340, 96, 80, 1)
+    for algo in ("rs", "gsw"):
+        g = run(ctx, algo, p, 3)
+        v = as_complex(to_np(g.V))[0]
+        assert abs(abs(v) - 1) < 1e-5 and abs(np.angle(v / np.exp(1j * p.theta0[0]))) < 1e-5
+        np.testing.assert_allclose(g.stats[:, :2], 1.0, atol=1e-5)
+
+
+def test_mirror_symmetry(ctx):
+    p = W.c1()
+    th = W.c1_mirror_theta(p.theta0)
+    r = ctx.hot_gsw(p.slm, p.xyz, th, 5)
+    torch.cuda.synchronize()
+    phi = to_np(r.phase)
+    # Mirror pixels see bit-identical terms, summed in a different trap order; the GSW map
+    # amplifies that rounding-level asymmetry (the FP64 oracle shows ~1e6 growth over 10
+    # iterations, from 1e-16 to 1e-10), so the FP32 bar is the parity tolerance at K = 5.
+    d = wrapped_diff(phi, phi[:, ::-1])
+    assert (d <= 1e-3).mean() >= 0.999 and d.max() < 1e-2
+    assert np.max(wrapped_diff(phi, phi[::-1, :])) > 0.1  # rows are not symmetric
+    A = np.abs(as_complex(to_np(r.V)))
+    for j in range(4):
+        for i in range(2):
+            assert abs(A[4 * j + i] - A[4 * j + 3 - i]) <= 1e-4 * A[4 * j + i]
+
+
+def test_resume_is_bitwise(ctx):
+    p = W.random_problem(350, 256, 256, 24)
+    full = ctx.hot_gsw(p.slm, p.xyz, p.theta0, 9)
+    a = ctx.hot_gsw(p.slm, p.xyz, p.theta0, 4, state=True)
+    b = ctx.hot_gsw(p.slm, p.xyz, to_np(a.theta), 5, w0=a.w.clone())
+    torch.cuda.synchronize()
+    assert torch.equal(full.phase, b.phase)
+    assert torch.equal(full.V, b.V)
+
+
+def test_runs_are_bitwise_deterministic(ctx):
+    p = W.c2()
+    a = ctx.hot_gsw(p.slm, p.xyz, p.theta0, 5)
+    b = ctx.hot_gsw(p.slm, p.xyz, p.theta0, 5)
+    torch.cuda.synchronize()
+    assert torch.equal(a.phase, b.phase) and torch.equal(a.V, b.V)
+
+
+def test_seeded_theta_matches_splitmix(ctx):
+    p = W.random_problem(360, 128, 96, 12)
+    g = ctx.hot_rs(p.slm, p.xyz, None, seed=987654321)
+    torch.cuda.synchronize()
+    o = oracle.solve("rs", p.slm, p.xyz, oracle.theta_seed(p.m, 987654321))
+    assert_phase(to_np(g.phase), o["phi"])
+    assert_V(to_np(g.V), o["V"])
+
+
+def test_large_phase_range_uses_explicit_reduction(ctx):
+    """Traps 0.4-0.6 mm off axis push |Delta| past the hardware sin/cos domain (256 rev): the
+    explicit fract() path must keep parity."""
+    rng = np.random.default_rng(370)
+    xyz = np.column_stack([rng.uniform(4e-4, 6e-4, 6), rng.uniform(-6e-4, -4e-4, 6), rng.uniform(-1e-5, 1e-5, 6)])
+    p = W.Problem(W.Slm(256, 256), xyz, rng.uniform(0, 2 * math.pi, 6), 4)
+    g = run(ctx, "gsw", p)
+    o = oracle.solve("gsw", p.slm, p.xyz, p.theta0, p.iters)
+    assert_phase(to_np(g.phase), o["phi"], tol=3e-3)
+    assert_V(to_np(g.V), o["V"], rtol=3e-4)
+
+
+@pytest.mark.parametrize("algo", ["rs", "gsw"])
+def test_max_traps(ctx, algo):
+    """HOT_MAX_TRAPS traps (several trap chunks per block, full LDS tables): a 46 x 46 planar
+    grid (3 um pitch, 2.2 resolution cells) cut to 2048 traps on a 256^2 SLM, so every trap is
+    resolved and the smallest |V_m| stays well above FP32 rounding."""
+    p = W.Problem(W.Slm(256, 256), W.square_grid(46, 3e-6)[:2048], W.random_phases(381, 2048), 2)
+    g = run(ctx, algo, p, 2)
+    o = oracle.solve(algo, p.slm, p.xyz, p.theta0, 2)
+    assert_phase(to_np(g.phase), o["phi"])
+    assert_V(to_np(g.V), o["V"])
+
+
+def test_bad_arguments_on_gpu(hot, ctx):
+    p = W.random_problem(390, 32, 32, 4)
+    with pytest.raises(hot.HotError) as e:
+        ctx.hot_gsw(p.slm, p.xyz, p.theta0, -1)
+    assert e.value.code == hot.HOT_EINVAL
+    bad = p.xyz.copy()
+    bad[1, 2] = np.nan
+    with pytest.raises(hot.HotError):
+        ctx.hot_rs(p.slm, bad, p.theta0)
+    with pytest.raises(hot.HotError):
+        ctx.hot_rs(W.Slm(0, 4), p.xyz, p.theta0)
