@@ -91,13 +91,16 @@ int hot_destroy(hot_ctx* ctx);
 int hot_set_stream(hot_ctx* ctx, void* stream);
 /* Select HOT_ONTHEFLY or HOT_STORED for later calls (hot_rs, hot_gs, hot_gsw). */
 int hot_set_variant(hot_ctx* ctx, int variant);
-/* Launch-shape knobs (used by the autotuner; 0 restores the built-in choice).  They
- * change how work is tiled, never what is computed beyond FP32 summation order. */
+/* Launch-shape knobs (used by the autotuner; 0 restores the built-in choice, except
+ * HOT_TUNE_GRAPHS).  They change how work is tiled or launched, never what is computed
+ * beyond FP32 summation order. */
 enum hot_tuning_key {
   HOT_TUNE_PIXELS_PER_LANE = 1, /* pixel pass: pixels per lane, 1, 2 or 4 */
   HOT_TUNE_TRAPS_PER_LANE = 2,  /* trap pass: traps each lane accumulates, 1..8 */
   HOT_TUNE_SEGMENT = 3,         /* trap pass: pixels of a row per block, 64..1024 */
-  HOT_TUNE_SLICES = 4           /* trap pass: at most this many pixel slices per wave, 1..16 */
+  HOT_TUNE_SLICES = 4,          /* trap pass: at most this many pixel slices per wave, 1..16 */
+  HOT_TUNE_GRAPHS = 5           /* 1 (default): replay a captured hipGraph of a solve's launch
+                                   sequence when shapes and buffers repeat; 0: launch eagerly */
 };
 int hot_set_tuning(hot_ctx* ctx, int key, int value);
 

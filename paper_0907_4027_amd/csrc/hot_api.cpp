@@ -63,6 +63,15 @@ struct hot_ctx {
   hipStream_t own_stream = nullptr;
   int variant = HOT_ONTHEFLY;
   int tune_q = 0, tune_tpl = 0, tune_seg = 0, tune_amax = 0;
+  int use_graphs = 1;
+  // captured launch sequences of solve(), keyed by everything they bake in (shapes, pointers)
+  struct GraphEntry {
+    std::vector<uint64_t> key;
+    hipGraphExec_t exec = nullptr;
+    uint64_t last_use = 0;
+  };
+  std::vector<GraphEntry> graphs;
+  uint64_t graph_clock = 0;
   DevBuf coef, st, hd, partial, stats, flag, amat, efield;
   Staging ring[kRing];
   int ring_pos = 0;
@@ -403,31 +412,83 @@ int solve(hot_ctx* c, const hot_slm* slm, int B, const int32_t* counts, const do
   const float inv_n = (float)(1.0 / (double)P.n);
   const int upd = algo == kGSW ? 2 : 1;
 
-  if (!stored) {
-    IterArgs a = iter_args(c, P, phase, K);
-    for (int k = 0; k <= K; ++k) {
-      a.upd = k == 0 ? 0 : upd;
-      a.st_in = k == 0 ? st[0] : st[(k - 1) & 1];
-      a.st_out = st[k & 1];
-      a.Vprev = V;
-      a.kstat = k - 1;
-      HIP_TRY(launch_iter(c->stream, a));
-      HIP_TRY(launch_reduce(c->stream, B, P.mmax, nblk, inv_n, part, hd, V));
+  // The K-iteration launch sequence (2 kernels per iteration on the on-the-fly path).
+  auto enqueue = [&](hipStream_t s) -> hipError_t {
+    hipError_t e = hipSuccess;
+    if (!stored) {
+      IterArgs a = iter_args(c, P, phase, K);
+      for (int k = 0; k <= K && e == hipSuccess; ++k) {
+        a.upd = k == 0 ? 0 : upd;
+        a.st_in = k == 0 ? st[0] : st[(k - 1) & 1];
+        a.st_out = st[k & 1];
+        a.Vprev = V;
+        a.kstat = k - 1;
+        e = launch_iter(s, a);
+        if (e == hipSuccess) e = launch_reduce(s, B, P.mmax, nblk, inv_n, part, hd, V);
+      }
+    } else {
+      for (int k = 0; k <= K && e == hipSuccess; ++k) {
+        if (k > 0)
+          e = launch_update(s, B, V, hd, st[(k - 1) & 1], st[k & 1], dstats, k - 1, K + 1, upd, (int*)c->flag.p);
+        if (e == hipSuccess)
+          e = launch_backward_stored(s, P.n, B, (const float2*)c->amat.p, st[k & 1], hd, phase, (float2*)c->efield.p);
+        if (e == hipSuccess)
+          e = launch_forward_stored(s, P.n, B, (const float2*)c->amat.p, (const float2*)c->efield.p, hd, part);
+        if (e == hipSuccess) e = launch_reduce(s, B, P.mmax, nblk, inv_n, part, hd, V);
+      }
     }
-  } else {
-    for (int k = 0; k <= K; ++k) {
-      if (k > 0)
-        HIP_TRY(launch_update(c->stream, B, V, hd, st[(k - 1) & 1], st[k & 1], dstats, k - 1, K + 1, upd,
-                              (int*)c->flag.p));
-      HIP_TRY(launch_backward_stored(c->stream, P.n, B, (const float2*)c->amat.p, st[k & 1], hd, phase,
-                                     (float2*)c->efield.p));
-      HIP_TRY(launch_forward_stored(c->stream, P.n, B, (const float2*)c->amat.p, (const float2*)c->efield.p, hd,
-                                    part));
-      HIP_TRY(launch_reduce(c->stream, B, P.mmax, nblk, inv_n, part, hd, V));
+    if (e == hipSuccess) e = launch_update(s, B, V, hd, st[K & 1], st[K & 1], dstats, K, K + 1, 0, (int*)c->flag.p);
+    if (e == hipSuccess && (w_out || theta_out)) e = launch_export_state(s, st[K & 1], P.T, w_out, theta_out);
+    return e;
+  };
+
+  // Replay a captured graph of the sequence when one with the same shapes and pointers
+  // exists (captured on the context's own stream, launched on the caller's).
+  bool done = false;
+  if (c->use_graphs) {
+    std::vector<uint64_t> key = {(uint64_t)B, (uint64_t)P.T, (uint64_t)P.nx, (uint64_t)P.ny, (uint64_t)K,
+                                 (uint64_t)algo, (uint64_t)variant, (uint64_t)P.fract, (uint64_t)P.nt, (uint64_t)P.q,
+                                 (uint64_t)P.tpl, (uint64_t)P.fg.seg_w, (uint64_t)(uintptr_t)phase,
+                                 (uint64_t)(uintptr_t)V, (uint64_t)(uintptr_t)w_out, (uint64_t)(uintptr_t)theta_out,
+                                 (uint64_t)(uintptr_t)c->coef.p, (uint64_t)(uintptr_t)c->st.p,
+                                 (uint64_t)(uintptr_t)c->hd.p, (uint64_t)(uintptr_t)c->partial.p,
+                                 (uint64_t)(uintptr_t)c->stats.p, (uint64_t)(uintptr_t)c->amat.p,
+                                 (uint64_t)(uintptr_t)c->efield.p};
+    hot_ctx::GraphEntry* hit = nullptr;
+    for (auto& g : c->graphs)
+      if (g.key == key) hit = &g;
+    if (!hit) {
+      hipGraph_t graph = nullptr;
+      hipGraphExec_t exec = nullptr;
+      bool ok = hipStreamBeginCapture(c->own_stream, hipStreamCaptureModeThreadLocal) == hipSuccess;
+      if (ok) {
+        const hipError_t e = enqueue(c->own_stream);
+        const hipError_t e2 = hipStreamEndCapture(c->own_stream, &graph);
+        ok = e == hipSuccess && e2 == hipSuccess && graph &&
+             hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) == hipSuccess;
+        if (graph) (void)hipGraphDestroy(graph);
+      }
+      if (!ok) {  // capture not available: run eagerly from now on
+        (void)hipGetLastError();
+        c->use_graphs = 0;
+      } else {
+        if (c->graphs.size() >= 8) {
+          auto lru = std::min_element(c->graphs.begin(), c->graphs.end(),
+                                      [](const auto& x, const auto& y) { return x.last_use < y.last_use; });
+          (void)hipGraphExecDestroy(lru->exec);
+          c->graphs.erase(lru);
+        }
+        c->graphs.push_back({std::move(key), exec, 0});
+        hit = &c->graphs.back();
+      }
+    }
+    if (hit) {
+      hit->last_use = ++c->graph_clock;
+      HIP_TRY(hipGraphLaunch(hit->exec, c->stream));
+      done = true;
     }
   }
-  HIP_TRY(launch_update(c->stream, B, V, hd, st[K & 1], st[K & 1], dstats, K, K + 1, 0, (int*)c->flag.p));
-  if (w_out || theta_out) HIP_TRY(launch_export_state(c->stream, st[K & 1], P.T, w_out, theta_out));
+  if (!done) HIP_TRY(enqueue(c->stream));
   if (stats) {
     HIP_TRY(hipMemcpyAsync(stats, dstats, sizeof(float) * 3 * (size_t)B * (K + 1), hipMemcpyDeviceToHost,
                            c->stream));
@@ -511,6 +572,7 @@ int hot_destroy(hot_ctx* c) {
   if (!c) return HOT_OK;
   (void)hipSetDevice(c->device);
   (void)hipStreamSynchronize(c->stream);
+  for (auto& g : c->graphs) (void)hipGraphExecDestroy(g.exec);
   for (DevBuf* b : {&c->coef, &c->st, &c->hd, &c->partial, &c->stats, &c->flag, &c->amat, &c->efield})
     if (b->p) (void)hipFree(b->p);
   for (auto& s : c->ring) {
@@ -551,6 +613,10 @@ int hot_set_tuning(hot_ctx* c, int key, int value) {
     case HOT_TUNE_SEGMENT:
       if (value != 0 && (value < 64 || value > 1024)) return fail(HOT_EINVAL, "segment must be 0 or 64..1024");
       c->tune_seg = value;
+      return HOT_OK;
+    case HOT_TUNE_GRAPHS:
+      if (value != 0 && value != 1) return fail(HOT_EINVAL, "graphs must be 0 or 1");
+      c->use_graphs = value;
       return HOT_OK;
     case HOT_TUNE_SLICES:
       if (value < 0 || value > 16) return fail(HOT_EINVAL, "slices must be 0..16");

@@ -93,6 +93,10 @@ class Context:
                          (_lib.HOT_TUNE_SEGMENT, segment), (_lib.HOT_TUNE_SLICES, slices)):
             check(self._lib, self._lib.hot_set_tuning(self._ctx, key, int(val)))
 
+    def set_graphs(self, enabled: bool) -> None:
+        """Replay captured hipGraphs of repeated solves (default) or launch eagerly."""
+        check(self._lib, self._lib.hot_set_tuning(self._ctx, _lib.HOT_TUNE_GRAPHS, int(bool(enabled))))
+
     def set_stream(self, stream=None) -> None:
         if isinstance(stream, torch.cuda.Stream):
             stream = stream.cuda_stream

@@ -303,3 +303,32 @@ def test_bad_arguments_on_gpu(hot, ctx):
         ctx.hot_rs(p.slm, bad, p.theta0)
     with pytest.raises(hot.HotError):
         ctx.hot_rs(W.Slm(0, 4), p.xyz, p.theta0)
+
+
+def test_graph_replays_match_eager(hot):
+    """The cached hipGraph of a solve, replayed several times with other eager work and
+    synchronisations in between, reproduces the eager launch sequence bit for bit each time."""
+    p = W.c2()
+    q = W.random_problem(400, 300, 77, 37, 4)
+    with hot.Context(0) as eager, hot.Context(0) as graphed:
+        eager.set_graphs(False)
+        ref = eager.hot_gsw(p.slm, p.xyz, p.theta0, 6, state=True)
+        ref_q = eager.hot_gsw(q.slm, q.xyz, q.theta0, q.iters)
+        torch.cuda.synchronize()
+        phase = torch.empty(p.slm.ny, p.slm.nx, device="cuda")
+        V = torch.empty(p.m, 2, device="cuda")
+        for rep in range(4):
+            r = graphed.hot_gsw(p.slm, p.xyz, p.theta0, 6, phase=phase, V=V, state=True)
+            torch.cuda.synchronize()
+            assert torch.equal(r.phase, ref.phase), rep
+            assert torch.equal(r.V, ref.V), rep
+            assert torch.equal(r.w, ref.w) and torch.equal(r.theta, ref.theta), rep
+            np.testing.assert_array_equal(r.stats, ref.stats)
+            # eager work on the same device between replays: torch ops and another problem
+            junk = torch.randn(1 << 20, device="cuda").sum()
+            rq = graphed.hot_gsw(q.slm, q.xyz, q.theta0, q.iters)
+            torch.cuda.synchronize()
+            assert torch.equal(rq.phase, ref_q.phase) and torch.equal(rq.V, ref_q.V)
+            phase.zero_()
+            V.zero_()
+            del junk
