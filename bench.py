@@ -58,7 +58,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-extra", action="store_true", help="skip batched / adjoint / stored comparisons")
-    ap.add_argument("--only", choices=["main", "passes", "batched", "adjoint", "stored"], default=None,
+    ap.add_argument("--only", choices=["main", "passes", "batched", "adjoint", "stored", "interactive"], default=None,
                     help="run one section only (for profiler runs)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -195,6 +195,29 @@ def main():
                                       "trap": round(bytes_pass / (pm[3] * 1e-3) / 1e9, 1)},
                          "hbm_peak_GBs": HBM_PEAK_GBS}
         log(f"[bench] stored variant {tsd:.4f} ms/step")
+
+    # ---------------------------------------------------------------- interactive: rotating cube, 5 GSW iterations per frame
+    if not args.no_extra and args.only in (None, "interactive"):
+        from paper_0907_4027_amd.interactive import RealtimeLoop
+        islm = W.Slm(1024, 768)
+        loop = RealtimeLoop(ctx, islm, 8, iters=5)
+        th0 = W.random_phases(600, 8)
+        lat = []
+        for f in range(96 + 4):
+            frame, Vh, dt = loop.frame(W.rotating_cube(f, 96), th0)
+            if f >= 4:
+                lat.append(dt)
+        lat = np.array(lat) * 1e3
+        I = (Vh.numpy().astype(np.float64) ** 2).sum(1)
+        out["interactive"] = {"workload": "rotating 5 um cube, 8 traps, 1024x768 SLM, 5 warm-started GSW iterations "
+                                          "per frame, 8-bit frame copied to pinned host memory",
+                              "frames": int(lat.size), "frame_ms_mean": round(float(lat.mean()), 4),
+                              "frame_ms_p50": round(float(np.median(lat)), 4),
+                              "frame_ms_p99": round(float(np.quantile(lat, 0.99)), 4),
+                              "frames_per_s": round(float(1e3 / lat.mean()), 1),
+                              "last_frame_efficiency": round(float(I.sum()), 4),
+                              "last_frame_uniformity": round(float(1 - (I.max() - I.min()) / (I.max() + I.min())), 4)}
+        log(f"[bench] interactive frame {lat.mean():.3f} ms mean, p99 {np.quantile(lat, 0.99):.3f} ms")
 
     # ---------------------------------------------------------------- CPU oracle on a bounded sample
     cpu = None

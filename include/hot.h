@@ -165,6 +165,15 @@ int hot_forward_V(hot_ctx* ctx, const hot_slm* slm, int32_t B, const int32_t* M,
 int hot_adjoint(hot_ctx* ctx, const hot_slm* slm, int32_t B, const int32_t* M, const double* xyz,
                 const float* phase, const float* G, float* grad_phase);
 
+/* ---- SLM output ----------------------------------------------------------------------- */
+
+/* 8-bit SLM frame (Section 5: each grey level maps linearly onto a phase from 0 to 2 pi):
+ *   frame[j] = rint(phase[j] * 256 / (2 pi)) mod 256,
+ * with the product taken in FP32 (FP32(256 / (2 pi)) times the FP32 phase, rounded to
+ * nearest even), so a phase of 2 pi encodes as 0.  phase: device, n floats (radians, as
+ * written by the solvers); frame: device, n bytes.  Asynchronous on the context's stream. */
+int hot_encode_u8(hot_ctx* ctx, int64_t n, const float* phase, uint8_t* frame);
+
 /* ---- diagnostics ---------------------------------------------------------------------- */
 
 /* Measurement aid for benchmarks and profilers: for the single-hologram problem given,

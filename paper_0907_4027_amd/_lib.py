@@ -18,7 +18,7 @@ HOT_TUNE_PIXELS_PER_LANE, HOT_TUNE_TRAPS_PER_LANE, HOT_TUNE_SEGMENT, HOT_TUNE_SL
 
 # every symbol include/hot.h declares
 EXPORTS = ("hot_create", "hot_destroy", "hot_set_stream", "hot_set_variant", "hot_set_tuning", "hot_sync", "hot_check_problem",
-           "hot_rs", "hot_gs", "hot_gsw", "hot_gsw_batched", "hot_forward_V", "hot_adjoint", "hot_time_passes",
+           "hot_rs", "hot_gs", "hot_gsw", "hot_gsw_batched", "hot_forward_V", "hot_adjoint", "hot_encode_u8", "hot_time_passes",
            "hot_last_error", "hot_abi_version")
 
 
@@ -68,6 +68,7 @@ def load(path: str = LIB_PATH):
         "hot_gsw_batched": ([P, S, i32, ip, dp, dp, i32, P, P, ST], C.c_int),
         "hot_forward_V": ([P, S, i32, ip, dp, P, P], C.c_int),
         "hot_adjoint": ([P, S, i32, ip, dp, P, P, P], C.c_int),
+        "hot_encode_u8": ([P, C.c_int64, P, P], C.c_int),
         "hot_time_passes": ([P, S, i32, dp, dp, i32, P, P, C.POINTER(C.c_float)], C.c_int),
         "hot_last_error": ([], C.c_char_p),
         "hot_abi_version": ([], C.c_int),

@@ -712,6 +712,17 @@ int hot_adjoint(hot_ctx* c, const hot_slm* slm, int32_t B, const int32_t* M, con
   return HOT_OK;
 }
 
+int hot_encode_u8(hot_ctx* c, int64_t n, const float* phase, uint8_t* frame) {
+  if (!c) return fail(HOT_EINVAL, "ctx is NULL");
+  if (n < 1 || n > (int64_t)HOT_MAX_SIDE * HOT_MAX_SIDE * HOT_MAX_BATCH)
+    return fail(HOT_EINVAL, "pixel count %lld out of range", (long long)n);
+  if (!phase || !frame) return fail(HOT_EINVAL, "phase and frame pointers are required");
+  int rc;
+  if ((rc = set_dev(c))) return rc;
+  HIP_TRY(launch_encode_u8(c->stream, phase, frame, n));
+  return HOT_OK;
+}
+
 int hot_time_passes(hot_ctx* c, const hot_slm* slm, int32_t M, const double* xyz, const double* theta0,
                     int32_t reps, float* phase, float* V, float* ms) {
   if (!c) return fail(HOT_EINVAL, "ctx is NULL");

@@ -105,6 +105,9 @@ hipError_t launch_backward_stored(hipStream_t s, int n, int B, const float2* A, 
 hipError_t launch_forward_stored(hipStream_t s, int n, int B, const float2* A, const float2* E, const HoloDesc* hd,
                                  float2* partial);
 
+// 8-bit SLM frame encoding.
+hipError_t launch_encode_u8(hipStream_t s, const float* phase, uint8_t* frame, int64_t n);
+
 // Small helpers.
 hipError_t launch_fill_u32(hipStream_t s, unsigned* p, unsigned v, int n);
 hipError_t launch_export_state(hipStream_t s, const TrapState* st, int t, float* w_out, float* theta_out);

@@ -556,6 +556,16 @@ k_forward_stored(const float2* __restrict__ A, const float2* __restrict__ E, con
 
 // ------------------------------------------------------------------ helpers
 
+// 8-bit SLM frame: grey level = rint(phase * 256 / (2 pi)) mod 256 (FP32 product, round to even).
+__global__ void __launch_bounds__(256) k_encode_u8(const float* __restrict__ phase, uint8_t* __restrict__ frame,
+                                                   int64_t n) {
+  constexpr float kLevelsPerRad = 40.7436654315252059f;  // FP32(256 / (2 pi))
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+    const int level = (int)__builtin_rintf(phase[i] * kLevelsPerRad);
+    frame[i] = (uint8_t)(level & 255);
+  }
+}
+
 __global__ void k_fill_u32(unsigned* p, unsigned v, int n) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) p[i] = v;
@@ -709,6 +719,12 @@ hipError_t launch_forward_stored(hipStream_t s, int n, int B, const float2* A, c
   const int nblk = stored_nblk(n);
   dim3 grid((nblk + 3) / 4, B);
   hipLaunchKernelGGL(k_forward_stored<kStoredPpl>, grid, dim3(kBlock), 0, s, A, E, hd, n, partial);
+  return hipGetLastError();
+}
+
+hipError_t launch_encode_u8(hipStream_t s, const float* phase, uint8_t* frame, int64_t n) {
+  const int64_t blocks = std::min<int64_t>((n + 255) / 256, 4096);
+  hipLaunchKernelGGL(k_encode_u8, dim3((unsigned)std::max<int64_t>(blocks, 1)), dim3(256), 0, s, phase, frame, n);
   return hipGetLastError();
 }
 

@@ -145,7 +145,9 @@ class Context:
         return Result(phase, V, _stats_np(st, (iters + 1, 3)))
 
     def hot_gsw(self, slm, xyz, theta0=None, iters: int = 10, seed: int = 0, w0=None, phase=None, V=None,
-                stats: bool = True, state: bool = False) -> Result:
+                stats: bool = True, state: bool = False, w_out=None, theta_out=None) -> Result:
+        """GSW; with state=True the final weights and trap phases are returned (written into
+        w_out / theta_out when given, e.g. to reuse buffers frame after frame)."""
         s = as_slm(slm)
         x = _host_f64(xyz, cols=3)
         M = x.shape[0]
@@ -153,8 +155,8 @@ class Context:
         w0 = self._dev(w0, M, "w0")
         phase = self._dev(phase, s.nx * s.ny, "phase") if phase is not None else self._new(s.ny, s.nx)
         V = self._dev(V, 2 * M, "V") if V is not None else self._new(M, 2)
-        w_out = self._new(M) if state else None
-        th_out = self._new(M) if state else None
+        w_out = self._dev(w_out, M, "w_out") if w_out is not None else (self._new(M) if state else None)
+        th_out = self._dev(theta_out, M, "theta_out") if theta_out is not None else (self._new(M) if state else None)
         st = (hot_stats * (iters + 1))() if stats else None
         check(self._lib, self._lib.hot_gsw(self._ctx, C.byref(s), M, _dp(x), _dp(th), C.c_uint64(seed), int(iters),
                                            _vp(w0), _vp(w_out), _vp(th_out), _vp(phase), _vp(V), st))
@@ -185,6 +187,19 @@ class Context:
         check(self._lib, self._lib.hot_forward_V(self._ctx, C.byref(s), B, cnt.ctypes.data_as(C.POINTER(C.c_int32)),
                                                  _dp(x), _vp(phase), _vp(V)))
         return V
+
+    def hot_encode_u8(self, phase: torch.Tensor, frame: Optional[torch.Tensor] = None) -> torch.Tensor:
+        """8-bit SLM frame of a phase mask: rint(phase * 256 / 2 pi) mod 256 (device uint8)."""
+        if not (phase.is_cuda and phase.device == self.device and phase.dtype == torch.float32
+                and phase.is_contiguous()):
+            raise ValueError(f"phase must be a contiguous float32 tensor on {self.device}")
+        if frame is None:
+            frame = torch.empty(phase.shape, dtype=torch.uint8, device=self.device)
+        elif not (frame.dtype == torch.uint8 and frame.is_contiguous() and frame.numel() == phase.numel()
+                  and frame.device == self.device):
+            raise ValueError("frame must be a contiguous uint8 tensor with as many elements as phase")
+        check(self._lib, self._lib.hot_encode_u8(self._ctx, phase.numel(), _vp(phase), _vp(frame)))
+        return frame
 
     def hot_time_passes(self, slm, xyz, theta0, reps: int = 20) -> np.ndarray:
         """Mean device ms per launch of [iteration kernel, reduce, pixel pass alone, trap pass alone]."""

@@ -23,7 +23,7 @@ def lib():
 def declared_functions():
     text = open(HEADER).read()
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    return sorted(set(re.findall(r"\b(hot_[a-z_A-Z]+)\s*\(", text)))
+    return sorted(set(re.findall(r"\b(hot_[A-Za-z0-9_]+)\s*\(", text)))
 
 
 def test_header_and_binding_agree():
