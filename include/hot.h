@@ -76,7 +76,9 @@ enum hot_status {
 /* How the propagation phase Delta is obtained inside the two passes. */
 enum hot_variant {
   HOT_ONTHEFLY = 0, /* Delta recomputed per (pixel, trap) with FP32 sin/cos (default) */
-  HOT_STORED = 1    /* exp(i Delta) precomputed once as a complex64 [M][N] matrix, then two GEMV-shaped passes */
+  HOT_STORED = 1,   /* exp(i Delta) precomputed once as a complex64 [M][N] matrix, then two GEMV-shaped passes */
+  HOT_SEPARABLE = 2 /* exact factorisation exp(i Delta) = X_m(column) Y_m(row): both passes become complex
+                       GEMMs (rocBLAS, FP32) plus O(N) and O((nx+ny) M) kernels; single holograms only */
 };
 
 /* ---- context ------------------------------------------------------------------------ */
@@ -89,7 +91,7 @@ int hot_create(hot_ctx** out, int device, void* stream);
 int hot_destroy(hot_ctx* ctx);
 /* Switch the stream later calls enqueue on (NULL: the default stream). */
 int hot_set_stream(hot_ctx* ctx, void* stream);
-/* Select HOT_ONTHEFLY or HOT_STORED for later calls (hot_rs, hot_gs, hot_gsw). */
+/* Select HOT_ONTHEFLY, HOT_STORED or HOT_SEPARABLE for later calls (hot_rs, hot_gs, hot_gsw). */
 int hot_set_variant(hot_ctx* ctx, int variant);
 /* Launch-shape knobs (used by the autotuner; 0 restores the built-in choice, except
  * HOT_TUNE_GRAPHS).  They change how work is tiled or launched, never what is computed
@@ -180,10 +182,11 @@ int hot_encode_u8(hot_ctx* ctx, int64_t n, const float* phase, uint8_t* frame);
  * launches four groups of kernels `reps` times each, back to back on the context's stream
  * (current variant and tuning), each group bracketed by HIP events, and writes the mean
  * device time per launch in milliseconds to
- *   ms[0]  one GSW iteration's main kernel (on-the-fly: the fused update + pixel pass +
- *          trap pass kernel; stored: the pixel pass and trap pass kernels)
- *   ms[1]  the fixed-order reduction of the trap-pass partials into V
- *   ms[2]  the pixel pass alone      ms[3]  the trap pass alone
+ *   ms[0]  one GSW iteration's main work (on-the-fly: the fused update + pixel pass + trap
+ *          pass kernel; stored: the pixel and trap pass kernels; separable: the whole step)
+ *   ms[1]  the reduction of the trap-pass partials into V (separable: V collection, update
+ *          and weighted rows)
+ *   ms[2]  the pixel pass alone (separable: GEMM + phase)   ms[3]  the trap pass alone
  * phase (device, N floats) and V (device, 2M floats) are scratch outputs.  Synchronises
  * the stream. */
 int hot_time_passes(hot_ctx* ctx, const hot_slm* slm, int32_t M, const double* xyz, const double* theta0,

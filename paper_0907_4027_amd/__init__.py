@@ -6,11 +6,11 @@ micro-manipulation using optimized holograms generated on the GPU"
 include/hot.h.  This package only marshals arguments into that library.
 """
 from ._lib import (HOT_EDEGENERATE, HOT_EDEVICE, HOT_EINVAL, HOT_ENOMEM, HOT_MAX_BATCH, HOT_MAX_SIDE,
-                   HOT_MAX_TRAPS, HOT_OK, HOT_ONTHEFLY, HOT_STORED, HotError, hot_slm, hot_stats, load)
+                   HOT_MAX_TRAPS, HOT_OK, HOT_ONTHEFLY, HOT_SEPARABLE, HOT_STORED, HotError, hot_slm, hot_stats, load)
 
 __all__ = ["Context", "Result", "TrapField", "trap_intensity_loss", "optimize_phase", "HotError", "hot_slm",
            "hot_stats", "load", "HOT_OK", "HOT_EINVAL", "HOT_ENOMEM", "HOT_EDEVICE", "HOT_EDEGENERATE",
-           "HOT_ONTHEFLY", "HOT_STORED", "HOT_MAX_TRAPS", "HOT_MAX_SIDE", "HOT_MAX_BATCH"]
+           "HOT_ONTHEFLY", "HOT_STORED", "HOT_SEPARABLE", "HOT_MAX_TRAPS", "HOT_MAX_SIDE", "HOT_MAX_BATCH"]
 
 
 def __getattr__(name):

@@ -12,7 +12,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libhot.so")
 
 HOT_OK, HOT_EINVAL, HOT_ENOMEM, HOT_EDEVICE, HOT_EDEGENERATE = 0, -1, -2, -3, -4
-HOT_ONTHEFLY, HOT_STORED = 0, 1
+HOT_ONTHEFLY, HOT_STORED, HOT_SEPARABLE = 0, 1, 2
 HOT_MAX_TRAPS, HOT_MAX_SIDE, HOT_MAX_BATCH = 2048, 4096, 4096
 HOT_TUNE_PIXELS_PER_LANE, HOT_TUNE_TRAPS_PER_LANE, HOT_TUNE_SEGMENT, HOT_TUNE_SLICES, HOT_TUNE_GRAPHS = 1, 2, 3, 4, 5
 

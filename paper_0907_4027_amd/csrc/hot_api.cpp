@@ -6,6 +6,7 @@
 #include "hot_internal.h"
 
 #include <hip/hip_runtime.h>
+#include <rocblas/rocblas.h>
 
 #include <algorithm>
 #include <cmath>
@@ -73,6 +74,10 @@ struct hot_ctx {
   std::vector<GraphEntry> graphs;
   uint64_t graph_clock = 0;
   DevBuf coef, st, hd, partial, stats, flag, amat, efield;
+  // separable variant: X, conj X [M][nx], Y, Yw [M][ny], S, E [N], T [M][ny] (complex64)
+  DevBuf sx, sxc, sy, syw, ss, se, stt;
+  bool sep_valid = false;
+  rocblas_handle blas = nullptr;
   Staging ring[kRing];
   int ring_pos = 0;
   int* flag_host = nullptr;  // pinned
@@ -338,6 +343,7 @@ int upload_tables(hot_ctx* c, const hot_slm* slm, const Plan& P, const double* x
   if (key == c->key && c->coef.p && c->hd.p) return HOT_OK;
   c->key.clear();
   c->amat_valid = false;
+  c->sep_valid = false;
   if ((rc = ensure(c, c->coef, sizeof(TrapCoef) * P.T))) return rc;
   if ((rc = ensure(c, c->hd, sizeof(HoloDesc) * 2 * P.B))) return rc;
   if ((rc = upload(c, c->coef.p, c->h_coef.data(), sizeof(TrapCoef) * P.T))) return rc;
@@ -371,6 +377,53 @@ int ensure_stored(hot_ctx* c, const Plan& P) {
   return HOT_OK;
 }
 
+#define BLAS_TRY(expr)                                                                      \
+  do {                                                                                      \
+    rocblas_status s_ = (expr);                                                             \
+    if (s_ != rocblas_status_success)                                                       \
+      return fail(HOT_EDEVICE, "%s failed: %s", #expr, rocblas_status_to_string(s_));        \
+  } while (0)
+
+// The two complex GEMMs of the separable path (rocBLAS is column-major; a row-major [ny][nx]
+// array is its nx x ny matrix):
+//   pixel pass  S[r][c] = sum_m Yw[m][r] X[m][c]            (C = X_cm Yw_cm^T,     nx x ny)
+//   trap pass   T[m][r] = sum_c E[r][c] conj X[m][c]        (C = E_cm^T Xc_cm,     ny x M)
+rocblas_status sep_gemms(hot_ctx* c, const Plan& P, hipStream_t s, bool first, bool second) {
+  const rocblas_float_complex one = {1.0f, 0.0f}, zero = {0.0f, 0.0f};
+  rocblas_status st = rocblas_set_stream(c->blas, s);
+  if (st == rocblas_status_success && first)
+    st = rocblas_cgemm(c->blas, rocblas_operation_none, rocblas_operation_transpose, P.nx, P.ny, P.T, &one,
+                       (const rocblas_float_complex*)c->sx.p, P.nx, (const rocblas_float_complex*)c->syw.p, P.ny,
+                       &zero, (rocblas_float_complex*)c->ss.p, P.nx);
+  if (st == rocblas_status_success && second)
+    st = rocblas_cgemm(c->blas, rocblas_operation_transpose, rocblas_operation_none, P.ny, P.T, P.nx, &one,
+                       (const rocblas_float_complex*)c->se.p, P.nx, (const rocblas_float_complex*)c->sxc.p, P.nx,
+                       &zero, (rocblas_float_complex*)c->stt.p, P.ny);
+  return st;
+}
+
+int ensure_separable(hot_ctx* c, const Plan& P) {
+  int rc;
+  if (P.B != 1) return fail(HOT_EINVAL, "the separable variant solves single holograms");
+  if (!c->blas) BLAS_TRY(rocblas_create_handle(&c->blas));
+  const size_t f2 = sizeof(float2);
+  if ((rc = ensure(c, c->sx, f2 * (size_t)P.T * P.nx))) return rc;
+  if ((rc = ensure(c, c->sxc, f2 * (size_t)P.T * P.nx))) return rc;
+  if ((rc = ensure(c, c->sy, f2 * (size_t)P.T * P.ny))) return rc;
+  if ((rc = ensure(c, c->syw, f2 * (size_t)P.T * P.ny))) return rc;
+  if ((rc = ensure(c, c->ss, f2 * (size_t)P.n))) return rc;
+  if ((rc = ensure(c, c->se, f2 * (size_t)P.n))) return rc;
+  if ((rc = ensure(c, c->stt, f2 * (size_t)P.ny * P.T))) return rc;
+  if (!c->sep_valid) {
+    HIP_TRY(launch_sep_tables(c->stream, P.fract, (const TrapCoef*)c->coef.p, P.T, P.nx, P.ny, (float2*)c->sx.p,
+                              (float2*)c->sxc.p, (float2*)c->sy.p));
+    // one eager pass so that rocBLAS finishes any lazy set-up before a graph capture
+    BLAS_TRY(sep_gemms(c, P, c->stream, true, true));
+    c->sep_valid = true;
+  }
+  return HOT_OK;
+}
+
 IterArgs iter_args(hot_ctx* c, const Plan& P, float* phase, int K) {
   IterArgs a;
   a.fg = P.fg;
@@ -398,11 +451,14 @@ int solve(hot_ctx* c, const hot_slm* slm, int B, const int32_t* counts, const do
   if ((rc = prepare(c, slm, B, counts, xyz, theta0, seeded, seed, P))) return rc;
   const int K = algo == kRS ? 0 : iters;
   const bool stored = variant == HOT_STORED;
+  const bool separable = variant == HOT_SEPARABLE;
   const int nblk = stored ? P.nblk_stored : P.fg.nblk();
+  if (separable && B != 1) return fail(HOT_EINVAL, "the separable variant solves single holograms");
   if ((rc = upload_tables(c, slm, P, xyz, counts))) return rc;
   if ((rc = ensure(c, c->partial, sizeof(float2) * (size_t)P.T * nblk))) return rc;
   if ((rc = ensure(c, c->stats, sizeof(float) * 3 * (size_t)B * (K + 1)))) return rc;
   if (stored && (rc = ensure_stored(c, P))) return rc;
+  if (separable && (rc = ensure_separable(c, P))) return rc;
   TrapState* st[2] = {(TrapState*)c->st.p, (TrapState*)c->st.p + P.T};
   if (w0) HIP_TRY(launch_import_w(c->stream, w0, st[0], P.T));
 
@@ -415,6 +471,26 @@ int solve(hot_ctx* c, const hot_slm* slm, int B, const int32_t* counts, const do
   // The K-iteration launch sequence (2 kernels per iteration on the on-the-fly path).
   auto enqueue = [&](hipStream_t s) -> hipError_t {
     hipError_t e = hipSuccess;
+    if (separable) {
+      float2* Yw = (float2*)c->syw.p;
+      const float2* Y = (const float2*)c->sy.p;
+      const float2* T = (const float2*)c->stt.p;
+      e = launch_sep_weights(s, V, Y, P.T, P.ny, 0, st[0], st[0], nullptr, (int*)c->flag.p, Yw);
+      for (int k = 0; k <= K && e == hipSuccess; ++k) {
+        if (sep_gemms(c, P, s, true, false) != rocblas_status_success) return hipErrorUnknown;
+        e = launch_sep_phase(s, (const float2*)c->ss.p, P.n, phase, (float2*)c->se.p);
+        if (e != hipSuccess) break;
+        if (sep_gemms(c, P, s, false, true) != rocblas_status_success) return hipErrorUnknown;
+        e = launch_sep_collect(s, T, Y, P.T, P.ny, inv_n, V);
+        if (e == hipSuccess && k < K)
+          e = launch_sep_weights(s, V, Y, P.T, P.ny, upd, st[k & 1], st[(k + 1) & 1], dstats + 3 * k, (int*)c->flag.p,
+                                 Yw);
+      }
+      if (e == hipSuccess)
+        e = launch_update(s, 1, V, hd, st[K & 1], st[K & 1], dstats, K, K + 1, 0, (int*)c->flag.p);
+      if (e == hipSuccess && (w_out || theta_out)) e = launch_export_state(s, st[K & 1], P.T, w_out, theta_out);
+      return e;
+    }
     if (!stored) {
       IterArgs a = iter_args(c, P, phase, K);
       for (int k = 0; k <= K && e == hipSuccess; ++k) {
@@ -453,7 +529,10 @@ int solve(hot_ctx* c, const hot_slm* slm, int B, const int32_t* counts, const do
                                  (uint64_t)(uintptr_t)c->coef.p, (uint64_t)(uintptr_t)c->st.p,
                                  (uint64_t)(uintptr_t)c->hd.p, (uint64_t)(uintptr_t)c->partial.p,
                                  (uint64_t)(uintptr_t)c->stats.p, (uint64_t)(uintptr_t)c->amat.p,
-                                 (uint64_t)(uintptr_t)c->efield.p};
+                                 (uint64_t)(uintptr_t)c->efield.p, (uint64_t)(uintptr_t)c->sx.p, (uint64_t)(uintptr_t)c->sxc.p,
+                                 (uint64_t)(uintptr_t)c->sy.p, (uint64_t)(uintptr_t)c->syw.p,
+                                 (uint64_t)(uintptr_t)c->ss.p, (uint64_t)(uintptr_t)c->se.p,
+                                 (uint64_t)(uintptr_t)c->stt.p};
     hot_ctx::GraphEntry* hit = nullptr;
     for (auto& g : c->graphs)
       if (g.key == key) hit = &g;
@@ -573,13 +652,15 @@ int hot_destroy(hot_ctx* c) {
   (void)hipSetDevice(c->device);
   (void)hipStreamSynchronize(c->stream);
   for (auto& g : c->graphs) (void)hipGraphExecDestroy(g.exec);
-  for (DevBuf* b : {&c->coef, &c->st, &c->hd, &c->partial, &c->stats, &c->flag, &c->amat, &c->efield})
+  for (DevBuf* b : {&c->coef, &c->st, &c->hd, &c->partial, &c->stats, &c->flag, &c->amat, &c->efield, &c->sx, &c->sxc, &c->sy, &c->syw,
+                    &c->ss, &c->se, &c->stt})
     if (b->p) (void)hipFree(b->p);
   for (auto& s : c->ring) {
     if (s.pending && s.ev) (void)hipEventSynchronize(s.ev);
     if (s.host) (void)hipHostFree(s.host);
     if (s.ev) (void)hipEventDestroy(s.ev);
   }
+  if (c->blas) (void)rocblas_destroy_handle(c->blas);
   if (c->flag_host) (void)hipHostFree(c->flag_host);
   if (c->own_stream) (void)hipStreamDestroy(c->own_stream);
   delete c;
@@ -594,7 +675,8 @@ int hot_set_stream(hot_ctx* c, void* stream) {
 
 int hot_set_variant(hot_ctx* c, int variant) {
   if (!c) return fail(HOT_EINVAL, "ctx is NULL");
-  if (variant != HOT_ONTHEFLY && variant != HOT_STORED) return fail(HOT_EINVAL, "unknown variant %d", variant);
+  if (variant != HOT_ONTHEFLY && variant != HOT_STORED && variant != HOT_SEPARABLE)
+    return fail(HOT_EINVAL, "unknown variant %d", variant);
   c->variant = variant;
   return HOT_OK;
 }
@@ -734,11 +816,59 @@ int hot_time_passes(hot_ctx* c, const hot_slm* slm, int32_t M, const double* xyz
   Plan P;
   if ((rc = prepare(c, slm, 1, &M, xyz, theta0, false, 0, P))) return rc;
   const bool stored = c->variant == HOT_STORED;
+  const bool separable = c->variant == HOT_SEPARABLE;
   const int nblk = stored ? P.nblk_stored : std::max(P.fg.nblk(), P.fgf.nblk());
   if ((rc = upload_tables(c, slm, P, xyz, &M))) return rc;
   if ((rc = ensure(c, c->partial, sizeof(float2) * (size_t)P.T * nblk))) return rc;
   if ((rc = ensure(c, c->stats, sizeof(float) * 3 * 2))) return rc;
   if (stored && (rc = ensure_stored(c, P))) return rc;
+  if (separable) {
+    if ((rc = ensure_separable(c, P))) return rc;
+    TrapState* st[2] = {(TrapState*)c->st.p, (TrapState*)c->st.p + P.T};
+    const float inv_n = (float)(1.0 / (double)P.n);
+    float2* Yw = (float2*)c->syw.p;
+    const float2* Y = (const float2*)c->sy.p;
+    const float2* T = (const float2*)c->stt.p;
+    auto upd = [&](bool init) -> hipError_t {
+      if (init) return launch_sep_weights(c->stream, V, Y, P.T, P.ny, 0, st[0], st[0], nullptr, (int*)c->flag.p, Yw);
+      hipError_t e = launch_sep_collect(c->stream, T, Y, P.T, P.ny, inv_n, V);
+      if (e != hipSuccess) return e;
+      return launch_sep_weights(c->stream, V, Y, P.T, P.ny, 2, st[0], st[1], (float*)c->stats.p, (int*)c->flag.p, Yw);
+    };
+    auto pix = [&]() -> hipError_t {
+      if (sep_gemms(c, P, c->stream, true, false) != rocblas_status_success) return hipErrorUnknown;
+      return launch_sep_phase(c->stream, (const float2*)c->ss.p, P.n, phase, (float2*)c->se.p);
+    };
+    auto trp = [&]() -> hipError_t {
+      return sep_gemms(c, P, c->stream, false, true) == rocblas_status_success ? hipSuccess : hipErrorUnknown;
+    };
+    if (upd(true) != hipSuccess || pix() != hipSuccess || trp() != hipSuccess)
+      return fail(HOT_EDEVICE, "launch failed");
+    hipEvent_t ev[5];
+    for (auto& e : ev) HIP_TRY(hipEventCreate(&e));
+    int out = HOT_OK;
+    (void)hipEventRecord(ev[0], c->stream);
+    for (int i = 0; i < reps && out == HOT_OK; ++i)
+      if (upd(false) != hipSuccess || pix() != hipSuccess || trp() != hipSuccess) out = fail(HOT_EDEVICE, "launch failed");
+    (void)hipEventRecord(ev[1], c->stream);
+    for (int i = 0; i < reps && out == HOT_OK; ++i) if (upd(false) != hipSuccess) out = fail(HOT_EDEVICE, "launch failed");
+    (void)hipEventRecord(ev[2], c->stream);
+    for (int i = 0; i < reps && out == HOT_OK; ++i) if (pix() != hipSuccess) out = fail(HOT_EDEVICE, "launch failed");
+    (void)hipEventRecord(ev[3], c->stream);
+    for (int i = 0; i < reps && out == HOT_OK; ++i) if (trp() != hipSuccess) out = fail(HOT_EDEVICE, "launch failed");
+    (void)hipEventRecord(ev[4], c->stream);
+    if (out == HOT_OK && hipEventSynchronize(ev[4]) == hipSuccess) {
+      for (int k = 0; k < 4; ++k) {
+        float t = 0.0f;
+        (void)hipEventElapsedTime(&t, ev[k], ev[k + 1]);
+        ms[k] = t / (float)reps;
+      }
+    } else if (out == HOT_OK) {
+      out = fail(HOT_EDEVICE, "event sync failed");
+    }
+    for (auto& e : ev) (void)hipEventDestroy(e);
+    return out;
+  }
   const TrapCoef* coef = (const TrapCoef*)c->coef.p;
   TrapState* st[2] = {(TrapState*)c->st.p, (TrapState*)c->st.p + P.T};
   const HoloDesc* hd = (const HoloDesc*)c->hd.p;

@@ -105,6 +105,16 @@ hipError_t launch_backward_stored(hipStream_t s, int n, int B, const float2* A, 
 hipError_t launch_forward_stored(hipStream_t s, int n, int B, const float2* A, const float2* E, const HoloDesc* hd,
                                  float2* partial);
 
+// Separable reformulation (single hologram): tables X, conj X [M][nx] and Y [M][ny]
+// (complex64); V collection from the trap-pass GEMM output T [M][ny]; the weighted rows
+// Yw [M][ny] with the GS/GSW update; phase and E = e^{i phase} from S [ny][nx].
+hipError_t launch_sep_tables(hipStream_t s, bool fract, const TrapCoef* coef, int M, int nx, int ny, float2* X,
+                             float2* Xc, float2* Y);
+hipError_t launch_sep_collect(hipStream_t s, const float2* T, const float2* Y, int M, int ny, float inv_n, float* V);
+hipError_t launch_sep_weights(hipStream_t s, const float* V, const float2* Y, int M, int ny, int upd,
+                              const TrapState* st_in, TrapState* st_out, float* stats_row, int* flag, float2* Yw);
+hipError_t launch_sep_phase(hipStream_t s, const float2* S, int n, float* phase, float2* E);
+
 // 8-bit SLM frame encoding.
 hipError_t launch_encode_u8(hipStream_t s, const float* phase, uint8_t* frame, int64_t n);
 

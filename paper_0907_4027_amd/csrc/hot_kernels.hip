@@ -554,6 +554,105 @@ k_forward_stored(const float2* __restrict__ A, const float2* __restrict__ E, con
   }
 }
 
+// ------------------------------------------------------------------ separable reformulation
+//
+// Eq. 2 separates per trap: Delta_rev = (g U^2 + a U) + (g V^2 + b V), so
+//   e^{i 2pi Delta_j^m} = X_m(c) Y_m(r),  X_m(c) = e^{i 2pi (g U_c^2 + a U_c)},  Y_m(r) = e^{i 2pi (g V_r^2 + b V_r)}.
+// The pixel pass becomes S[r][c] = sum_m (w_m e^{i theta_m} Y_m(r)) X_m(c) (a rank-M complex
+// GEMM) and the trap pass T[r][m] = sum_c e^{i phi[r][c]} conj X_m(c) (a GEMM), then
+// V_m = (1/N) sum_r conj Y_m(r) T[r][m].  Same sums as the direct passes, with N*M
+// transcendentals replaced by (nx + ny)*M; the GEMMs run in rocBLAS (FP32 complex).
+
+// X [M][nx], conj X [M][nx] and Y [M][ny] (complex64, trap-major) for one hologram;
+// grid (ceil(max(nx,ny)/256), M).
+template <bool FRACT>
+__global__ void __launch_bounds__(256)
+k_sep_tables(const TrapCoef* __restrict__ coef, int M, int nx, int ny, float2* __restrict__ X, float2* __restrict__ Xc,
+             float2* __restrict__ Y) {
+  const int m = blockIdx.y;
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  const TrapCoef c = coef[m];
+  if (i < nx) {
+    const float U = (float)(2 * i - (nx - 1));
+    const float t = to_period<FRACT>(__builtin_fmaf(c.g, U * U, c.a * U));
+    const float cs = __builtin_amdgcn_cosf(t), sn = __builtin_amdgcn_sinf(t);
+    X[(size_t)m * nx + i] = make_float2(cs, sn);
+    Xc[(size_t)m * nx + i] = make_float2(cs, -sn);
+  }
+  if (i < ny) {
+    const float Vr = (float)(2 * i - (ny - 1));
+    const float t = to_period<FRACT>(__builtin_fmaf(c.g, Vr * Vr, c.b * Vr));
+    Y[(size_t)m * ny + i] = make_float2(__builtin_amdgcn_cosf(t), __builtin_amdgcn_sinf(t));
+  }
+}
+
+// V_m = (1/N) sum_r conj Y_m(r) T[m][r]  (T trap-major [M][ny]); one wave per trap, lanes over
+// r, fixed order.  Grid ceil(M / 4) blocks of 256.
+__global__ void __launch_bounds__(256)
+k_sep_collect(const float2* __restrict__ T, const float2* __restrict__ Y, int M, int ny, float inv_n,
+              float* __restrict__ V) {
+  const int m = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+  if (m >= M) return;
+  float sr = 0.0f, si = 0.0f;
+  for (int r = lane; r < ny; r += 64) {
+    const float2 y = Y[(size_t)m * ny + r], t = T[(size_t)m * ny + r];
+    sr = __builtin_fmaf(y.x, t.x, __builtin_fmaf(y.y, t.y, sr));   // Re(conj(y) t)
+    si = __builtin_fmaf(y.x, t.y, __builtin_fmaf(-y.y, t.x, si));  // Im(conj(y) t)
+  }
+  sr = wave_sum(sr);
+  si = wave_sum(si);
+  if (lane == 0) {
+    V[2 * m] = sr * inv_n;
+    V[2 * m + 1] = si * inv_n;
+  }
+}
+
+// Weighted rows for the next pixel pass, Yw[m][r] = w_m e^{i 2pi theta_m} Y_m(r), with the GS/GSW
+// update recomputed by every block from V (as in the fused kernel).  Grid (ceil(ny / 256), M):
+// block (x, m) handles trap m, rows 256x ..; blocks with x = 0 write st_out[m]; block (0, 0)
+// writes the figures of merit of V.  upd = 0 takes the state as is (V is not read).
+__global__ void __launch_bounds__(256)
+k_sep_weights(const float* __restrict__ V, const float2* __restrict__ Y, int M, int ny, int upd,
+              const TrapState* __restrict__ st_in, TrapState* __restrict__ st_out, float* __restrict__ stats_row,
+              int* __restrict__ flag, float2* __restrict__ Yw) {
+  __shared__ float sh[8 * 4];
+  __shared__ float2 cm;
+  const int m = blockIdx.y, x = blockIdx.x;
+  if (upd == 0) {
+    if (threadIdx.x == 0) {
+      const TrapState s = st_in[m];
+      cm = make_float2(s.w * __builtin_amdgcn_cosf(s.theta_rev), s.w * __builtin_amdgcn_sinf(s.theta_rev));
+    }
+  } else {
+    const bool lead = x == 0 && m == 0;
+    update_traps<256>(V, st_in, 0, M, upd, sh, lead ? stats_row : nullptr, lead ? flag : nullptr,
+                      [&](int k, const TrapState& s) {
+                        if (k != m) return;
+                        if (x == 0) st_out[m] = s;
+                        cm = make_float2(s.w * __builtin_amdgcn_cosf(s.theta_rev), s.w * __builtin_amdgcn_sinf(s.theta_rev));
+                      });
+  }
+  __syncthreads();
+  const int r = x * 256 + threadIdx.x;
+  if (r < ny) {
+    const float2 c = cm, y = Y[(size_t)m * ny + r];
+    Yw[(size_t)m * ny + r] = make_float2(c.x * y.x - c.y * y.y, c.x * y.y + c.y * y.x);
+  }
+}
+
+// phase = arg S in [0, 2pi], E = e^{i phase} (via the FP32 phase in revolutions, as the trap pass
+// of the direct path reads it).
+__global__ void __launch_bounds__(256)
+k_sep_phase(const float2* __restrict__ S, int n, float* __restrict__ phase, float2* __restrict__ E) {
+  for (int i = blockIdx.x * 256 + threadIdx.x; i < n; i += gridDim.x * 256) {
+    const float2 s = S[i];
+    const float ph = wrap_phase(atan2f(s.y, s.x));
+    phase[i] = ph;
+    const float pr = ph * kInv2Pi;
+    E[i] = make_float2(__builtin_amdgcn_cosf(pr), __builtin_amdgcn_sinf(pr));
+  }
+}
+
 // ------------------------------------------------------------------ helpers
 
 // 8-bit SLM frame: grey level = rint(phase * 256 / (2 pi)) mod 256 (FP32 product, round to even).
@@ -719,6 +818,34 @@ hipError_t launch_forward_stored(hipStream_t s, int n, int B, const float2* A, c
   const int nblk = stored_nblk(n);
   dim3 grid((nblk + 3) / 4, B);
   hipLaunchKernelGGL(k_forward_stored<kStoredPpl>, grid, dim3(kBlock), 0, s, A, E, hd, n, partial);
+  return hipGetLastError();
+}
+
+hipError_t launch_sep_tables(hipStream_t s, bool fract, const TrapCoef* coef, int M, int nx, int ny, float2* X,
+                             float2* Xc, float2* Y) {
+  dim3 grid((std::max(nx, ny) + 255) / 256, M);
+  if (fract)
+    hipLaunchKernelGGL(k_sep_tables<true>, grid, dim3(256), 0, s, coef, M, nx, ny, X, Xc, Y);
+  else
+    hipLaunchKernelGGL(k_sep_tables<false>, grid, dim3(256), 0, s, coef, M, nx, ny, X, Xc, Y);
+  return hipGetLastError();
+}
+
+hipError_t launch_sep_collect(hipStream_t s, const float2* T, const float2* Y, int M, int ny, float inv_n, float* V) {
+  hipLaunchKernelGGL(k_sep_collect, dim3((M + 3) / 4), dim3(256), 0, s, T, Y, M, ny, inv_n, V);
+  return hipGetLastError();
+}
+
+hipError_t launch_sep_weights(hipStream_t s, const float* V, const float2* Y, int M, int ny, int upd,
+                              const TrapState* st_in, TrapState* st_out, float* stats_row, int* flag, float2* Yw) {
+  hipLaunchKernelGGL(k_sep_weights, dim3((ny + 255) / 256, M), dim3(256), 0, s, V, Y, M, ny, upd, st_in, st_out,
+                     stats_row, flag, Yw);
+  return hipGetLastError();
+}
+
+hipError_t launch_sep_phase(hipStream_t s, const float2* S, int n, float* phase, float2* E) {
+  const int blocks = std::min((n + 255) / 256, 2048);
+  hipLaunchKernelGGL(k_sep_phase, dim3(blocks), dim3(256), 0, s, S, n, phase, E);
   return hipGetLastError();
 }
 

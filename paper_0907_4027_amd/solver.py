@@ -12,7 +12,7 @@ import numpy as np
 import torch
 
 from . import _lib
-from ._lib import HOT_ONTHEFLY, HOT_STORED, check, hot_slm, hot_stats
+from ._lib import HOT_ONTHEFLY, HOT_SEPARABLE, HOT_STORED, check, hot_slm, hot_stats
 
 
 class Result(NamedTuple):
@@ -83,7 +83,7 @@ class Context:
 
     # -- configuration --------------------------------------------------------------
     def set_variant(self, variant) -> None:
-        v = {"onthefly": HOT_ONTHEFLY, "stored": HOT_STORED}.get(variant, variant)
+        v = {"onthefly": HOT_ONTHEFLY, "stored": HOT_STORED, "separable": HOT_SEPARABLE}.get(variant, variant)
         check(self._lib, self._lib.hot_set_variant(self._ctx, int(v)))
 
     def set_tuning(self, pixels_per_lane: int = 0, traps_per_lane: int = 0, segment: int = 0,

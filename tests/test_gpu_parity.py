@@ -31,6 +31,25 @@ def ctx(hot):
     c.close()
 
 
+_ORACLE = {}
+
+
+def oracle_solve(algo, p, iters):
+    """Oracle results are cached per (problem, algorithm, iterations): several variants compare to them."""
+    key = (algo, p.name, p.slm.nx, p.slm.ny, p.xyz.tobytes(), p.theta0.tobytes(), iters)
+    if key not in _ORACLE:
+        _ORACLE[key] = oracle.solve(algo, p.slm, p.xyz, p.theta0, iters)
+    return _ORACLE[key]
+
+
+@pytest.fixture(scope="module")
+def sep(hot):
+    c = hot.Context(0)
+    c.set_variant("separable")
+    yield c
+    c.close()
+
+
 def run(ctx, algo, p, iters=None, **kw):
     iters = p.iters if iters is None else iters
     if algo == "rs":
@@ -95,7 +114,7 @@ def test_gsw_256sq_4x4_grid_30_iterations(ctx):
 def test_512sq_100_traps_50_iterations(ctx, algo):
     p = W.c2()
     g = run(ctx, algo, p)
-    o = oracle.solve(algo, p.slm, p.xyz, p.theta0, p.iters)
+    o = oracle_solve(algo, p, p.iters)
     assert_phase(to_np(g.phase), o["phi"])
     assert_V(to_np(g.V), o["V"])
     assert_stats(g.stats, o["stats"])
@@ -377,3 +396,53 @@ def test_realtime_loop_warm_start_matches_oracle(hot, ctx):
         th_prev = loop.theta.copy()
         w_prev = to_np(loop.w)
         assert dt > 0
+
+
+# ------------------------------------------------------------------ separable reformulation (GEMM) variant
+
+SEP_CASES = {
+    "c1-256sq-16-k30": lambda: W.c1(),
+    "c2-512sq-100-k50": lambda: W.c2(),
+    "ragged-300x77-37-k6": lambda: W.random_problem(201, 300, 77, 37, 6),
+    "wide-1500x6-9-k6": lambda: W.random_problem(202, 1500, 6, 9, 6),
+    "tiny-3x5-1-k3": lambda: W.random_problem(204, 3, 5, 1, 3),
+}
+
+
+@pytest.mark.parametrize("name", sorted(SEP_CASES))
+@pytest.mark.parametrize("algo", ["rs", "gsw"])
+def test_separable_matches_oracle(sep, name, algo):
+    p = SEP_CASES[name]()
+    K = p.iters if algo == "gsw" else 0
+    g = run(sep, algo, p, K)
+    o = oracle_solve(algo, p, K)
+    assert_phase(to_np(g.phase), o["phi"], frac=0.999 if p.slm.n >= 64 else 1.0)
+    assert_V(to_np(g.V), o["V"])
+    assert_stats(g.stats, o["stats"])
+
+
+def test_separable_1024sq_256_traps(sep):
+    """Full 40-iteration run checked as for the direct path: final trap pass in full, final pixel
+    pass on sampled pixels, and the first 3 iterations in full."""
+    p = W.c3()
+    g = run(sep, "gsw", p, state=True)
+    phi = to_np(g.phase).ravel()
+    assert_V(to_np(g.V), oracle.forward(p.slm, p.xyz, phi), what="trap pass at K=40")
+    idx = np.random.default_rng(7).choice(p.slm.n, 4096, replace=False)
+    ref = oracle.backward(p.slm, p.xyz, to_np(g.w), to_np(g.theta).astype(np.float64), idx=idx)
+    assert_phase(phi[idx], ref, frac=0.998, what="pixel pass at K=40")
+    g3 = run(sep, "gsw", p, 3)
+    o3 = oracle_solve("gsw", p, 3)
+    assert_phase(to_np(g3.phase), o3["phi"])
+    assert_V(to_np(g3.V), o3["V"])
+
+
+def test_separable_resume_and_determinism(sep):
+    p = W.random_problem(410, 256, 256, 24)
+    full = sep.hot_gsw(p.slm, p.xyz, p.theta0, 9)
+    again = sep.hot_gsw(p.slm, p.xyz, p.theta0, 9)
+    a = sep.hot_gsw(p.slm, p.xyz, p.theta0, 4, state=True)
+    b = sep.hot_gsw(p.slm, p.xyz, to_np(a.theta), 5, w0=a.w.clone())
+    torch.cuda.synchronize()
+    assert torch.equal(full.phase, again.phase) and torch.equal(full.V, again.V)
+    assert torch.equal(full.phase, b.phase) and torch.equal(full.V, b.V)
