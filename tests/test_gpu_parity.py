@@ -446,3 +446,34 @@ def test_separable_resume_and_determinism(sep):
     torch.cuda.synchronize()
     assert torch.equal(full.phase, again.phase) and torch.equal(full.V, again.V)
     assert torch.equal(full.phase, b.phase) and torch.equal(full.V, b.V)
+
+
+def test_square_grid_sweep_case_matches_oracle(ctx):
+    """The 9 x 9 planar grid of the frame-budget sweep on a 768^2 SLM: RS, then one GSW
+    iteration, against the oracle (the paper's 20 Hz case for its GPU)."""
+    xyz = W.square_grid(9, 3e-6)
+    p = W.Problem(W.Slm(768, 768), xyz, W.random_phases(709, 81), 1, "sweep-9x9")
+    g = run(ctx, "gsw", p)
+    o = oracle_solve("gsw", p, 1)
+    assert_phase(to_np(g.phase), o["phi"])
+    assert_V(to_np(g.V), o["V"])
+    assert_stats(g.stats, o["stats"])
+    # one GSW iteration improves uniformity over random superposition (Section 5)
+    assert g.stats[1, 1] > g.stats[0, 1]
+
+
+def test_autotuner_caches_and_keeps_parity(hot, tmp_path):
+    from paper_0907_4027_amd import autotune
+    p = W.random_problem(420, 192, 160, 30, 4)
+    cache = str(tmp_path / "tuning.json")
+    with hot.Context(0) as c:
+        small = {"pixels_per_lane": (1, 2), "segment": (0,), "traps_per_lane": (0, 2, 4)}
+        rows = autotune.sweep(c, p.slm, p.xyz, p.theta0, reps=3, candidates=small)
+        assert len(rows) == 6 and rows[0]["iteration_us"] <= rows[-1]["iteration_us"]
+        r1 = autotune.tune(c, p.slm, p.xyz, p.theta0, cache=cache, reps=3)
+        r2 = autotune.tune(c, p.slm, p.xyz, p.theta0, cache=cache, reps=3)
+        assert r1["table"] is not None and r2["table"] is None and r1["knobs"] == r2["knobs"]
+        g = run(c, "gsw", p)
+    o = oracle_solve("gsw", p, p.iters)
+    assert_phase(to_np(g.phase), o["phi"])
+    assert_V(to_np(g.V), o["V"])
