@@ -77,8 +77,9 @@ enum hot_status {
 enum hot_variant {
   HOT_ONTHEFLY = 0, /* Delta recomputed per (pixel, trap) with FP32 sin/cos (default) */
   HOT_STORED = 1,   /* exp(i Delta) precomputed once as a complex64 [M][N] matrix, then two GEMV-shaped passes */
-  HOT_SEPARABLE = 2 /* exact factorisation exp(i Delta) = X_m(column) Y_m(row): both passes become complex
-                       GEMMs (rocBLAS, FP32) plus O(N) and O((nx+ny) M) kernels; single holograms only */
+  HOT_SEPARABLE = 2 /* exact factorisation of Eq. 2, exp(i Delta) = X_m(column) Y_m(row): both passes become
+                       dense complex contractions on the FP32 matrix cores, fused into one kernel per
+                       iteration, with O((nx+ny) M) tables; also used by the batched, Eq. 1 and adjoint calls */
 };
 
 /* ---- context ------------------------------------------------------------------------ */
@@ -91,7 +92,9 @@ int hot_create(hot_ctx** out, int device, void* stream);
 int hot_destroy(hot_ctx* ctx);
 /* Switch the stream later calls enqueue on (NULL: the default stream). */
 int hot_set_stream(hot_ctx* ctx, void* stream);
-/* Select HOT_ONTHEFLY, HOT_STORED or HOT_SEPARABLE for later calls (hot_rs, hot_gs, hot_gsw). */
+/* Select HOT_ONTHEFLY, HOT_STORED or HOT_SEPARABLE for later calls (hot_rs, hot_gs, hot_gsw;
+ * HOT_SEPARABLE also for hot_gsw_batched, hot_forward_V and hot_adjoint, which otherwise
+ * use the on-the-fly kernels). */
 int hot_set_variant(hot_ctx* ctx, int variant);
 /* Launch-shape knobs (used by the autotuner; 0 restores the built-in choice, except
  * HOT_TUNE_GRAPHS).  They change how work is tiled or launched, never what is computed
@@ -101,8 +104,12 @@ enum hot_tuning_key {
   HOT_TUNE_TRAPS_PER_LANE = 2,  /* trap pass: traps each lane accumulates, 1..8 */
   HOT_TUNE_SEGMENT = 3,         /* trap pass: pixels of a row per block, 64..1024 */
   HOT_TUNE_SLICES = 4,          /* trap pass: at most this many pixel slices per wave, 1..16 */
-  HOT_TUNE_GRAPHS = 5           /* 1 (default): replay a captured hipGraph of a solve's launch
+  HOT_TUNE_GRAPHS = 5,          /* 1 (default): replay a captured hipGraph of a solve's launch
                                    sequence when shapes and buffers repeat; 0: launch eagerly */
+  HOT_TUNE_SEP_WAVES = 6,       /* separable variant: waves per block (1, 2 or 4), each wave a tile
+                                   of 16 x 16 pixels */
+  HOT_TUNE_SEP_CHUNK = 7        /* separable variant: traps whose tables a block holds in LDS at
+                                   once, a multiple of 16 (more are streamed in chunks of this size) */
 };
 int hot_set_tuning(hot_ctx* ctx, int key, int value);
 
@@ -182,11 +189,10 @@ int hot_encode_u8(hot_ctx* ctx, int64_t n, const float* phase, uint8_t* frame);
  * launches four groups of kernels `reps` times each, back to back on the context's stream
  * (current variant and tuning), each group bracketed by HIP events, and writes the mean
  * device time per launch in milliseconds to
- *   ms[0]  one GSW iteration's main work (on-the-fly: the fused update + pixel pass + trap
- *          pass kernel; stored: the pixel and trap pass kernels; separable: the whole step)
- *   ms[1]  the reduction of the trap-pass partials into V (separable: V collection, update
- *          and weighted rows)
- *   ms[2]  the pixel pass alone (separable: GEMM + phase)   ms[3]  the trap pass alone
+ *   ms[0]  one GSW iteration's main work (on-the-fly and separable: the fused update + pixel
+ *          pass + trap pass kernel; stored: the pixel and trap pass kernels)
+ *   ms[1]  the reduction of the trap-pass partials into V
+ *   ms[2]  the pixel pass alone   ms[3]  the trap pass alone
  * phase (device, N floats) and V (device, 2M floats) are scratch outputs.  Synchronises
  * the stream. */
 int hot_time_passes(hot_ctx* ctx, const hot_slm* slm, int32_t M, const double* xyz, const double* theta0,

@@ -18,8 +18,7 @@ OUT = os.path.join(HERE, "libhot.so")
 # not know the feature, which is harmless
 FLAGS = ["-O3", "--offload-arch=gfx950", "-std=c++17", "-fPIC", "-shared",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-         "-I" + os.path.join(ROOT, "include"), "-I" + CSRC,
-         "-L/opt/rocm/lib", "-Wl,-rpath,/opt/rocm/lib", "-lrocblas"]
+         "-I" + os.path.join(ROOT, "include"), "-I" + CSRC]
 
 
 def hipcc() -> str:

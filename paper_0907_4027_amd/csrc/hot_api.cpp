@@ -6,7 +6,6 @@
 #include "hot_internal.h"
 
 #include <hip/hip_runtime.h>
-#include <rocblas/rocblas.h>
 
 #include <algorithm>
 #include <cmath>
@@ -63,7 +62,7 @@ struct hot_ctx {
   hipStream_t stream = nullptr;
   hipStream_t own_stream = nullptr;
   int variant = HOT_ONTHEFLY;
-  int tune_q = 0, tune_tpl = 0, tune_seg = 0, tune_amax = 0;
+  int tune_q = 0, tune_tpl = 0, tune_seg = 0, tune_amax = 0, tune_sepw = 0, tune_sepc = 0;
   int use_graphs = 1;
   // captured launch sequences of solve(), keyed by everything they bake in (shapes, pointers)
   struct GraphEntry {
@@ -74,10 +73,6 @@ struct hot_ctx {
   std::vector<GraphEntry> graphs;
   uint64_t graph_clock = 0;
   DevBuf coef, st, hd, partial, stats, flag, amat, efield;
-  // separable variant: X, conj X [M][nx], Y, Yw [M][ny], S, E [N], T [M][ny] (complex64)
-  DevBuf sx, sxc, sy, syw, ss, se, stt;
-  bool sep_valid = false;
-  rocblas_handle blas = nullptr;
   Staging ring[kRing];
   int ring_pos = 0;
   int* flag_host = nullptr;  // pinned
@@ -229,6 +224,8 @@ struct Plan {
   FwdGeom fgf{};
   int tplf = 1;
   int nblk_stored = 0;
+  // separable variant: blocks of 16 rows x 16 sep_w columns, sep_sc traps per LDS super-chunk
+  int sep_w = 4, nblk_sep = 0, sep_sc = 16;
 };
 
 FwdGeom row_segments(int nx, int ny, int segmax) {
@@ -264,6 +261,39 @@ int prepare(hot_ctx* c, const hot_slm* slm, int B, const int32_t* counts, const 
   }
   P.fgf = row_segments(slm->nx, slm->ny, c->tune_seg > 0 ? c->tune_seg : kSegMax);
   P.nblk_stored = stored_nblk(P.n);
+  {
+    // separable: the widest block (most waves sharing one update and one partial per trap) that
+    // still gives every compute unit a block
+    const int rows = (slm->ny + 15) / 16;
+    int w = c->tune_sepw;
+    if (w == 0) {
+      w = 1;
+      for (int cand : {4, 2}) {
+        const int cols = (slm->nx + 16 * cand - 1) / (16 * cand);
+        if ((int64_t)cols * rows * B >= 256) {
+          w = cand;
+          break;
+        }
+      }
+    }
+    P.sep_w = w;
+    P.nblk_sep = ((slm->nx + 16 * w - 1) / (16 * w)) * rows;
+    // traps per LDS super-chunk: all of them when they fit, with room for a second resident
+    // block per compute unit when the grid has more blocks than compute units
+    const int mp = (P.mmax + 15) / 16 * 16;
+    const size_t row_bytes = sep_lds_bytes(w, 16, P.mmax) - sep_lds_bytes(w, 0, P.mmax);  // per 16 traps
+    const size_t fixed = sep_lds_bytes(w, 0, P.mmax);
+    int sc = 16;
+    for (int bpc : {2, 1}) {
+      if (bpc == 2 && (int64_t)P.nblk_sep * B <= 256) continue;
+      const size_t budget = (size_t)kSepLdsMax / bpc;
+      if (budget <= fixed + row_bytes) continue;
+      sc = (int)std::min<size_t>(mp / 16, (budget - fixed) / row_bytes) * 16;
+      break;
+    }
+    if (c->tune_sepc > 0) sc = std::min(mp, c->tune_sepc);
+    P.sep_sc = std::max(16, sc);
+  }
 
   const double lf = slm->wavelength * slm->focal;
   const double ca = slm->pitch / (2.0 * lf);
@@ -334,6 +364,7 @@ int upload_tables(hot_ctx* c, const hot_slm* slm, const Plan& P, const double* x
   key.push_back(c->tune_tpl);
   key.push_back(c->tune_seg);
   key.push_back(c->tune_amax);
+  key.push_back(c->tune_sepw);
   key.push_back(P.B);
   for (int b = 0; b < P.B; ++b) key.push_back(counts[b]);
   key.insert(key.end(), xyz, xyz + 3 * (size_t)P.T);
@@ -343,7 +374,6 @@ int upload_tables(hot_ctx* c, const hot_slm* slm, const Plan& P, const double* x
   if (key == c->key && c->coef.p && c->hd.p) return HOT_OK;
   c->key.clear();
   c->amat_valid = false;
-  c->sep_valid = false;
   if ((rc = ensure(c, c->coef, sizeof(TrapCoef) * P.T))) return rc;
   if ((rc = ensure(c, c->hd, sizeof(HoloDesc) * 2 * P.B))) return rc;
   if ((rc = upload(c, c->coef.p, c->h_coef.data(), sizeof(TrapCoef) * P.T))) return rc;
@@ -377,51 +407,25 @@ int ensure_stored(hot_ctx* c, const Plan& P) {
   return HOT_OK;
 }
 
-#define BLAS_TRY(expr)                                                                      \
-  do {                                                                                      \
-    rocblas_status s_ = (expr);                                                             \
-    if (s_ != rocblas_status_success)                                                       \
-      return fail(HOT_EDEVICE, "%s failed: %s", #expr, rocblas_status_to_string(s_));        \
-  } while (0)
-
-// The two complex GEMMs of the separable path (rocBLAS is column-major; a row-major [ny][nx]
-// array is its nx x ny matrix):
-//   pixel pass  S[r][c] = sum_m Yw[m][r] X[m][c]            (C = X_cm Yw_cm^T,     nx x ny)
-//   trap pass   T[m][r] = sum_c E[r][c] conj X[m][c]        (C = E_cm^T Xc_cm,     ny x M)
-rocblas_status sep_gemms(hot_ctx* c, const Plan& P, hipStream_t s, bool first, bool second) {
-  const rocblas_float_complex one = {1.0f, 0.0f}, zero = {0.0f, 0.0f};
-  rocblas_status st = rocblas_set_stream(c->blas, s);
-  if (st == rocblas_status_success && first)
-    st = rocblas_cgemm(c->blas, rocblas_operation_none, rocblas_operation_transpose, P.nx, P.ny, P.T, &one,
-                       (const rocblas_float_complex*)c->sx.p, P.nx, (const rocblas_float_complex*)c->syw.p, P.ny,
-                       &zero, (rocblas_float_complex*)c->ss.p, P.nx);
-  if (st == rocblas_status_success && second)
-    st = rocblas_cgemm(c->blas, rocblas_operation_transpose, rocblas_operation_none, P.ny, P.T, P.nx, &one,
-                       (const rocblas_float_complex*)c->se.p, P.nx, (const rocblas_float_complex*)c->sxc.p, P.nx,
-                       &zero, (rocblas_float_complex*)c->stt.p, P.ny);
-  return st;
-}
-
-int ensure_separable(hot_ctx* c, const Plan& P) {
-  int rc;
-  if (P.B != 1) return fail(HOT_EINVAL, "the separable variant solves single holograms");
-  if (!c->blas) BLAS_TRY(rocblas_create_handle(&c->blas));
-  const size_t f2 = sizeof(float2);
-  if ((rc = ensure(c, c->sx, f2 * (size_t)P.T * P.nx))) return rc;
-  if ((rc = ensure(c, c->sxc, f2 * (size_t)P.T * P.nx))) return rc;
-  if ((rc = ensure(c, c->sy, f2 * (size_t)P.T * P.ny))) return rc;
-  if ((rc = ensure(c, c->syw, f2 * (size_t)P.T * P.ny))) return rc;
-  if ((rc = ensure(c, c->ss, f2 * (size_t)P.n))) return rc;
-  if ((rc = ensure(c, c->se, f2 * (size_t)P.n))) return rc;
-  if ((rc = ensure(c, c->stt, f2 * (size_t)P.ny * P.T))) return rc;
-  if (!c->sep_valid) {
-    HIP_TRY(launch_sep_tables(c->stream, P.fract, (const TrapCoef*)c->coef.p, P.T, P.nx, P.ny, (float2*)c->sx.p,
-                              (float2*)c->sxc.p, (float2*)c->sy.p));
-    // one eager pass so that rocBLAS finishes any lazy set-up before a graph capture
-    BLAS_TRY(sep_gemms(c, P, c->stream, true, true));
-    c->sep_valid = true;
-  }
-  return HOT_OK;
+SepArgs sep_args(hot_ctx* c, const Plan& P, int mode, float* phase, int K) {
+  SepArgs a;
+  a.mode = mode;
+  a.W = P.sep_w;
+  a.B = P.B;
+  a.nx = P.nx;
+  a.ny = P.ny;
+  a.mmax = P.mmax;
+  a.sc = P.sep_sc;
+  a.fract = P.fract;
+  a.coef = (const TrapCoef*)c->coef.p;
+  a.hd = (const HoloDesc*)c->hd.p;
+  a.stats = (float*)c->stats.p;
+  a.stat_stride = K + 1;
+  a.flag = (int*)c->flag.p;
+  a.inv_n = (float)(1.0 / (double)P.n);
+  a.phase = phase;
+  a.partial = (float2*)c->partial.p;
+  return a;
 }
 
 IterArgs iter_args(hot_ctx* c, const Plan& P, float* phase, int K) {
@@ -452,13 +456,11 @@ int solve(hot_ctx* c, const hot_slm* slm, int B, const int32_t* counts, const do
   const int K = algo == kRS ? 0 : iters;
   const bool stored = variant == HOT_STORED;
   const bool separable = variant == HOT_SEPARABLE;
-  const int nblk = stored ? P.nblk_stored : P.fg.nblk();
-  if (separable && B != 1) return fail(HOT_EINVAL, "the separable variant solves single holograms");
+  const int nblk = stored ? P.nblk_stored : separable ? P.nblk_sep : P.fg.nblk();
   if ((rc = upload_tables(c, slm, P, xyz, counts))) return rc;
   if ((rc = ensure(c, c->partial, sizeof(float2) * (size_t)P.T * nblk))) return rc;
   if ((rc = ensure(c, c->stats, sizeof(float) * 3 * (size_t)B * (K + 1)))) return rc;
   if (stored && (rc = ensure_stored(c, P))) return rc;
-  if (separable && (rc = ensure_separable(c, P))) return rc;
   TrapState* st[2] = {(TrapState*)c->st.p, (TrapState*)c->st.p + P.T};
   if (w0) HIP_TRY(launch_import_w(c->stream, w0, st[0], P.T));
 
@@ -472,26 +474,18 @@ int solve(hot_ctx* c, const hot_slm* slm, int B, const int32_t* counts, const do
   auto enqueue = [&](hipStream_t s) -> hipError_t {
     hipError_t e = hipSuccess;
     if (separable) {
-      float2* Yw = (float2*)c->syw.p;
-      const float2* Y = (const float2*)c->sy.p;
-      const float2* T = (const float2*)c->stt.p;
-      e = launch_sep_weights(s, V, Y, P.T, P.ny, 0, st[0], st[0], nullptr, (int*)c->flag.p, Yw);
+      SepArgs a = sep_args(c, P, 0, phase, K);
       for (int k = 0; k <= K && e == hipSuccess; ++k) {
-        if (sep_gemms(c, P, s, true, false) != rocblas_status_success) return hipErrorUnknown;
-        e = launch_sep_phase(s, (const float2*)c->ss.p, P.n, phase, (float2*)c->se.p);
-        if (e != hipSuccess) break;
-        if (sep_gemms(c, P, s, false, true) != rocblas_status_success) return hipErrorUnknown;
-        e = launch_sep_collect(s, T, Y, P.T, P.ny, inv_n, V);
-        if (e == hipSuccess && k < K)
-          e = launch_sep_weights(s, V, Y, P.T, P.ny, upd, st[k & 1], st[(k + 1) & 1], dstats + 3 * k, (int*)c->flag.p,
-                                 Yw);
+        a.upd = k == 0 ? 0 : upd;
+        a.st_in = k == 0 ? st[0] : st[(k - 1) & 1];
+        a.st_out = st[k & 1];
+        a.vin = V;
+        a.kstat = k - 1;
+        a.phase = k == K ? phase : nullptr;  // only the last mask's phase is returned
+        e = launch_sep(s, a);
+        if (e == hipSuccess) e = launch_reduce(s, B, P.mmax, nblk, inv_n, part, hd, V);
       }
-      if (e == hipSuccess)
-        e = launch_update(s, 1, V, hd, st[K & 1], st[K & 1], dstats, K, K + 1, 0, (int*)c->flag.p);
-      if (e == hipSuccess && (w_out || theta_out)) e = launch_export_state(s, st[K & 1], P.T, w_out, theta_out);
-      return e;
-    }
-    if (!stored) {
+    } else if (!stored) {
       IterArgs a = iter_args(c, P, phase, K);
       for (int k = 0; k <= K && e == hipSuccess; ++k) {
         a.upd = k == 0 ? 0 : upd;
@@ -524,15 +518,12 @@ int solve(hot_ctx* c, const hot_slm* slm, int B, const int32_t* counts, const do
   if (c->use_graphs) {
     std::vector<uint64_t> key = {(uint64_t)B, (uint64_t)P.T, (uint64_t)P.nx, (uint64_t)P.ny, (uint64_t)K,
                                  (uint64_t)algo, (uint64_t)variant, (uint64_t)P.fract, (uint64_t)P.nt, (uint64_t)P.q,
-                                 (uint64_t)P.tpl, (uint64_t)P.fg.seg_w, (uint64_t)(uintptr_t)phase,
+                                 (uint64_t)P.tpl, (uint64_t)P.fg.seg_w, (uint64_t)P.sep_w, (uint64_t)P.sep_sc, (uint64_t)(uintptr_t)phase,
                                  (uint64_t)(uintptr_t)V, (uint64_t)(uintptr_t)w_out, (uint64_t)(uintptr_t)theta_out,
                                  (uint64_t)(uintptr_t)c->coef.p, (uint64_t)(uintptr_t)c->st.p,
                                  (uint64_t)(uintptr_t)c->hd.p, (uint64_t)(uintptr_t)c->partial.p,
                                  (uint64_t)(uintptr_t)c->stats.p, (uint64_t)(uintptr_t)c->amat.p,
-                                 (uint64_t)(uintptr_t)c->efield.p, (uint64_t)(uintptr_t)c->sx.p, (uint64_t)(uintptr_t)c->sxc.p,
-                                 (uint64_t)(uintptr_t)c->sy.p, (uint64_t)(uintptr_t)c->syw.p,
-                                 (uint64_t)(uintptr_t)c->ss.p, (uint64_t)(uintptr_t)c->se.p,
-                                 (uint64_t)(uintptr_t)c->stt.p};
+                                 (uint64_t)(uintptr_t)c->efield.p};
     hot_ctx::GraphEntry* hit = nullptr;
     for (auto& g : c->graphs)
       if (g.key == key) hit = &g;
@@ -652,15 +643,13 @@ int hot_destroy(hot_ctx* c) {
   (void)hipSetDevice(c->device);
   (void)hipStreamSynchronize(c->stream);
   for (auto& g : c->graphs) (void)hipGraphExecDestroy(g.exec);
-  for (DevBuf* b : {&c->coef, &c->st, &c->hd, &c->partial, &c->stats, &c->flag, &c->amat, &c->efield, &c->sx, &c->sxc, &c->sy, &c->syw,
-                    &c->ss, &c->se, &c->stt})
+  for (DevBuf* b : {&c->coef, &c->st, &c->hd, &c->partial, &c->stats, &c->flag, &c->amat, &c->efield})
     if (b->p) (void)hipFree(b->p);
   for (auto& s : c->ring) {
     if (s.pending && s.ev) (void)hipEventSynchronize(s.ev);
     if (s.host) (void)hipHostFree(s.host);
     if (s.ev) (void)hipEventDestroy(s.ev);
   }
-  if (c->blas) (void)rocblas_destroy_handle(c->blas);
   if (c->flag_host) (void)hipHostFree(c->flag_host);
   if (c->own_stream) (void)hipStreamDestroy(c->own_stream);
   delete c;
@@ -699,6 +688,15 @@ int hot_set_tuning(hot_ctx* c, int key, int value) {
     case HOT_TUNE_GRAPHS:
       if (value != 0 && value != 1) return fail(HOT_EINVAL, "graphs must be 0 or 1");
       c->use_graphs = value;
+      return HOT_OK;
+    case HOT_TUNE_SEP_WAVES:
+      if (value != 0 && value != 1 && value != 2 && value != 4) return fail(HOT_EINVAL, "separable waves must be 0, 1, 2 or 4");
+      c->tune_sepw = value;
+      return HOT_OK;
+    case HOT_TUNE_SEP_CHUNK:
+      if (value < 0 || value > HOT_MAX_TRAPS || value % 16 != 0)
+        return fail(HOT_EINVAL, "separable chunk must be 0 or a multiple of 16 up to %d", HOT_MAX_TRAPS);
+      c->tune_sepc = value;
       return HOT_OK;
     case HOT_TUNE_SLICES:
       if (value < 0 || value > 16) return fail(HOT_EINVAL, "slices must be 0..16");
@@ -753,7 +751,7 @@ int hot_gsw_batched(hot_ctx* c, const hot_slm* slm, int32_t B, const int32_t* M,
   if (!theta0) return fail(HOT_EINVAL, "theta0 is required for batched calls");
   if (!phase || !V) return fail(HOT_EINVAL, "phase and V output pointers are required");
   return solve(c, slm, B, M, xyz, theta0, false, 0, kGSW, iters, nullptr, nullptr, nullptr, phase, V, stats,
-               HOT_ONTHEFLY);
+               c->variant == HOT_SEPARABLE ? HOT_SEPARABLE : HOT_ONTHEFLY);
 }
 
 int hot_forward_V(hot_ctx* c, const hot_slm* slm, int32_t B, const int32_t* M, const double* xyz,
@@ -768,6 +766,14 @@ int hot_forward_V(hot_ctx* c, const hot_slm* slm, int32_t B, const int32_t* M, c
   std::vector<double> zeros(T, 0.0);
   if ((rc = prepare(c, slm, B, M, xyz, zeros.data(), false, 0, P))) return rc;
   if ((rc = upload_tables(c, slm, P, xyz, M, false))) return rc;
+  if (c->variant == HOT_SEPARABLE) {
+    if ((rc = ensure(c, c->partial, sizeof(float2) * (size_t)P.T * P.nblk_sep))) return rc;
+    SepArgs a = sep_args(c, P, 1, const_cast<float*>(phase), 0);
+    HIP_TRY(launch_sep(c->stream, a));
+    HIP_TRY(launch_reduce(c->stream, B, P.mmax, P.nblk_sep, a.inv_n, (const float2*)c->partial.p,
+                          (const HoloDesc*)c->hd.p, V));
+    return HOT_OK;
+  }
   const int nblk = P.fgf.nblk();
   if ((rc = ensure(c, c->partial, sizeof(float2) * (size_t)P.T * nblk))) return rc;
   const HoloDesc* hdf = (const HoloDesc*)c->hd.p + B;
@@ -789,6 +795,13 @@ int hot_adjoint(hot_ctx* c, const hot_slm* slm, int32_t B, const int32_t* M, con
   std::vector<double> zeros(T, 0.0);
   if ((rc = prepare(c, slm, B, M, xyz, zeros.data(), false, 0, P))) return rc;
   if ((rc = upload_tables(c, slm, P, xyz, M, false))) return rc;
+  if (c->variant == HOT_SEPARABLE) {
+    SepArgs a = sep_args(c, P, 3, const_cast<float*>(phase), 0);
+    a.vin = G;
+    a.grad = grad_phase;
+    HIP_TRY(launch_sep(c->stream, a));
+    return HOT_OK;
+  }
   HIP_TRY(launch_backward(c->stream, P.nx, P.ny, B, P.fract, 1, (const TrapCoef*)c->coef.p, nullptr,
                           (const HoloDesc*)c->hd.p, const_cast<float*>(phase), 1, G, grad_phase));
   return HOT_OK;
@@ -817,58 +830,11 @@ int hot_time_passes(hot_ctx* c, const hot_slm* slm, int32_t M, const double* xyz
   if ((rc = prepare(c, slm, 1, &M, xyz, theta0, false, 0, P))) return rc;
   const bool stored = c->variant == HOT_STORED;
   const bool separable = c->variant == HOT_SEPARABLE;
-  const int nblk = stored ? P.nblk_stored : std::max(P.fg.nblk(), P.fgf.nblk());
+  const int nblk = stored ? P.nblk_stored : separable ? P.nblk_sep : std::max(P.fg.nblk(), P.fgf.nblk());
   if ((rc = upload_tables(c, slm, P, xyz, &M))) return rc;
   if ((rc = ensure(c, c->partial, sizeof(float2) * (size_t)P.T * nblk))) return rc;
   if ((rc = ensure(c, c->stats, sizeof(float) * 3 * 2))) return rc;
   if (stored && (rc = ensure_stored(c, P))) return rc;
-  if (separable) {
-    if ((rc = ensure_separable(c, P))) return rc;
-    TrapState* st[2] = {(TrapState*)c->st.p, (TrapState*)c->st.p + P.T};
-    const float inv_n = (float)(1.0 / (double)P.n);
-    float2* Yw = (float2*)c->syw.p;
-    const float2* Y = (const float2*)c->sy.p;
-    const float2* T = (const float2*)c->stt.p;
-    auto upd = [&](bool init) -> hipError_t {
-      if (init) return launch_sep_weights(c->stream, V, Y, P.T, P.ny, 0, st[0], st[0], nullptr, (int*)c->flag.p, Yw);
-      hipError_t e = launch_sep_collect(c->stream, T, Y, P.T, P.ny, inv_n, V);
-      if (e != hipSuccess) return e;
-      return launch_sep_weights(c->stream, V, Y, P.T, P.ny, 2, st[0], st[1], (float*)c->stats.p, (int*)c->flag.p, Yw);
-    };
-    auto pix = [&]() -> hipError_t {
-      if (sep_gemms(c, P, c->stream, true, false) != rocblas_status_success) return hipErrorUnknown;
-      return launch_sep_phase(c->stream, (const float2*)c->ss.p, P.n, phase, (float2*)c->se.p);
-    };
-    auto trp = [&]() -> hipError_t {
-      return sep_gemms(c, P, c->stream, false, true) == rocblas_status_success ? hipSuccess : hipErrorUnknown;
-    };
-    if (upd(true) != hipSuccess || pix() != hipSuccess || trp() != hipSuccess)
-      return fail(HOT_EDEVICE, "launch failed");
-    hipEvent_t ev[5];
-    for (auto& e : ev) HIP_TRY(hipEventCreate(&e));
-    int out = HOT_OK;
-    (void)hipEventRecord(ev[0], c->stream);
-    for (int i = 0; i < reps && out == HOT_OK; ++i)
-      if (upd(false) != hipSuccess || pix() != hipSuccess || trp() != hipSuccess) out = fail(HOT_EDEVICE, "launch failed");
-    (void)hipEventRecord(ev[1], c->stream);
-    for (int i = 0; i < reps && out == HOT_OK; ++i) if (upd(false) != hipSuccess) out = fail(HOT_EDEVICE, "launch failed");
-    (void)hipEventRecord(ev[2], c->stream);
-    for (int i = 0; i < reps && out == HOT_OK; ++i) if (pix() != hipSuccess) out = fail(HOT_EDEVICE, "launch failed");
-    (void)hipEventRecord(ev[3], c->stream);
-    for (int i = 0; i < reps && out == HOT_OK; ++i) if (trp() != hipSuccess) out = fail(HOT_EDEVICE, "launch failed");
-    (void)hipEventRecord(ev[4], c->stream);
-    if (out == HOT_OK && hipEventSynchronize(ev[4]) == hipSuccess) {
-      for (int k = 0; k < 4; ++k) {
-        float t = 0.0f;
-        (void)hipEventElapsedTime(&t, ev[k], ev[k + 1]);
-        ms[k] = t / (float)reps;
-      }
-    } else if (out == HOT_OK) {
-      out = fail(HOT_EDEVICE, "event sync failed");
-    }
-    for (auto& e : ev) (void)hipEventDestroy(e);
-    return out;
-  }
   const TrapCoef* coef = (const TrapCoef*)c->coef.p;
   TrapState* st[2] = {(TrapState*)c->st.p, (TrapState*)c->st.p + P.T};
   const HoloDesc* hd = (const HoloDesc*)c->hd.p;
@@ -880,7 +846,19 @@ int hot_time_passes(hot_ctx* c, const hot_slm* slm, int32_t M, const double* xyz
   a.st_in = st[0];
   a.st_out = st[1];
   a.Vprev = V;
+  SepArgs sa = sep_args(c, P, 0, phase, 1);
+  sa.upd = 2;
+  sa.st_in = st[0];
+  sa.st_out = st[1];
+  sa.vin = V;
+  auto sep_mode = [&](int mode) {
+    SepArgs x = sa;
+    x.mode = mode;
+    if (mode == 0) x.phase = nullptr;  // as in every iteration but the last
+    return launch_sep(c->stream, x);
+  };
   auto g0 = [&]() -> hipError_t {
+    if (separable) return sep_mode(0);
     if (!stored) return launch_iter(c->stream, a);
     hipError_t e = launch_backward_stored(c->stream, P.n, 1, (const float2*)c->amat.p, st[0], hd, phase,
                                           (float2*)c->efield.p);
@@ -888,14 +866,17 @@ int hot_time_passes(hot_ctx* c, const hot_slm* slm, int32_t M, const double* xyz
     return launch_forward_stored(c->stream, P.n, 1, (const float2*)c->amat.p, (const float2*)c->efield.p, hd, part);
   };
   auto g1 = [&]() {
-    return launch_reduce(c->stream, 1, P.mmax, stored ? P.nblk_stored : P.fg.nblk(), inv_n, part, hd, V);
+    return launch_reduce(c->stream, 1, P.mmax, stored ? P.nblk_stored : separable ? P.nblk_sep : P.fg.nblk(), inv_n,
+                         part, hd, V);
   };
   auto g2 = [&]() {
+    if (separable) return sep_mode(2);
     return stored ? launch_backward_stored(c->stream, P.n, 1, (const float2*)c->amat.p, st[0], hd, phase,
                                            (float2*)c->efield.p)
                   : launch_backward(c->stream, P.nx, P.ny, 1, P.fract, 1, coef, st[0], hd, phase, 0, nullptr, nullptr);
   };
   auto g3 = [&]() {
+    if (separable) return sep_mode(1);
     return stored ? launch_forward_stored(c->stream, P.n, 1, (const float2*)c->amat.p, (const float2*)c->efield.p, hd,
                                           part)
                   : launch_forward(c->stream, P.fgf, 1, P.tplf, P.fract, coef, hd + 1, phase, part);
@@ -906,8 +887,8 @@ int hot_time_passes(hot_ctx* c, const hot_slm* slm, int32_t M, const double* xyz
   do {
     // V must hold a real trap field before the fused kernel's update reads it
     if (g2() != hipSuccess || g3() != hipSuccess ||
-        launch_reduce(c->stream, 1, P.mmax, stored ? P.nblk_stored : P.fgf.nblk(), inv_n, part,
-                      stored ? hd : hd + 1, V) != hipSuccess ||
+        launch_reduce(c->stream, 1, P.mmax, stored ? P.nblk_stored : separable ? P.nblk_sep : P.fgf.nblk(), inv_n,
+                      part, stored || separable ? hd : hd + 1, V) != hipSuccess ||
         g0() != hipSuccess || g1() != hipSuccess) {
       out = fail(HOT_EDEVICE, "launch failed");
       break;

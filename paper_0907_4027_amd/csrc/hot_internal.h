@@ -105,15 +105,39 @@ hipError_t launch_backward_stored(hipStream_t s, int n, int B, const float2* A, 
 hipError_t launch_forward_stored(hipStream_t s, int n, int B, const float2* A, const float2* E, const HoloDesc* hd,
                                  float2* partial);
 
-// Separable reformulation (single hologram): tables X, conj X [M][nx] and Y [M][ny]
-// (complex64); V collection from the trap-pass GEMM output T [M][ny]; the weighted rows
-// Yw [M][ny] with the GS/GSW update; phase and E = e^{i phase} from S [ny][nx].
-hipError_t launch_sep_tables(hipStream_t s, bool fract, const TrapCoef* coef, int M, int nx, int ny, float2* X,
-                             float2* Xc, float2* Y);
-hipError_t launch_sep_collect(hipStream_t s, const float2* T, const float2* Y, int M, int ny, float inv_n, float* V);
-hipError_t launch_sep_weights(hipStream_t s, const float* V, const float2* Y, int M, int ny, int upd,
-                              const TrapState* st_in, TrapState* st_out, float* stats_row, int* flag, float2* Yw);
-hipError_t launch_sep_phase(hipStream_t s, const float2* S, int n, float* phase, float2* E);
+// Separable reformulation on the matrix cores (any batch); the per-block tables of Eq. 2's two
+// factors are computed in LDS from coef.
+struct SepArgs {
+  int mode = 0;  // 0 iteration, 1 trap pass from `phase`, 2 pixel pass, 3 adjoint (G in vin, grad out)
+  int W = 4;     // waves per block: a block covers 16 rows x 16 W columns
+  int B = 1, nx = 0, ny = 0, mmax = 0;
+  int sc = 16;   // traps per LDS super-chunk (multiple of 16); sep_lds_bytes(W, sc, mmax) <= kSepLdsMax
+  bool fract = false;
+  const TrapCoef* coef = nullptr;
+  const HoloDesc* hd = nullptr;
+  const TrapState* st_in = nullptr;
+  TrapState* st_out = nullptr;
+  const float* vin = nullptr;  // V of the previous mask (mode 0 with upd != 0) or G (mode 3), interleaved
+  float* stats = nullptr;
+  int kstat = 0, stat_stride = 1;
+  int upd = 0;  // mode 0: 0 none, 1 GS, 2 GSW
+  int* flag = nullptr;
+  float inv_n = 0.0f;
+  float* phase = nullptr;  // mode 0: written when non-null; modes 1, 3: read; mode 2: written
+  float* grad = nullptr;
+  float2* partial = nullptr;  // [T][nblk()]
+  int gx() const { return (nx + 16 * W - 1) / (16 * W); }
+  int gy() const { return (ny + 15) / 16; }
+  int nblk() const { return gx() * gy(); }
+};
+hipError_t launch_sep(hipStream_t s, const SepArgs& a);
+// dynamic LDS of a separable launch: per-trap coefficients and weights, the tables of sc traps
+// for the block's 16 W columns and 16 rows (plain and weighted), and W per-wave trap sums
+constexpr int kSepLdsMax = 160 * 1024 - 1024;
+inline size_t sep_lds_bytes(int W, int sc, int mmax) {
+  const size_t mp = (size_t)(mmax + 15) / 16 * 16;
+  return 24 * mp + 8 * (size_t)(sc + 2) * (16 * W + 32) + 8 * (size_t)W * sc;
+}
 
 // 8-bit SLM frame encoding.
 hipError_t launch_encode_u8(hipStream_t s, const float* phase, uint8_t* frame, int64_t n);

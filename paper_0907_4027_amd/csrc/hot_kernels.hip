@@ -106,13 +106,20 @@ __device__ __forceinline__ void block_reduce(float* sh, float& a, float& b, floa
 //   stats_row (3 floats) if non-null: e = sum I, u = 1 - (max-min)/(max+min), sigma = std(I)/mean(I)
 //   mode 0: no update; 1 (GS): theta_m <- arg V_m; 2 (GSW): also w_m <- w_m <|V|>/|V_m|
 // emit(m, state) is called once per trap m, by the thread that owns it.  <|V|> = 0 leaves
-// the state unchanged and raises *flag (if non-null).
-template <int NT, class Emit>
+// the state unchanged and raises *flag (if non-null).  With PRE, trap threadIdx.x's V and state
+// come from vpre / spre (loaded earlier by the caller) instead of memory.
+template <int NT, class Emit, bool PRE = false>
 __device__ void update_traps(const float* __restrict__ V, const TrapState* __restrict__ st_in, int off, int M,
-                             int mode, float* sh, float* stats_row, int* flag, Emit emit) {
+                             int mode, float* sh, float* stats_row, int* flag, Emit emit,
+                             float2 vpre = make_float2(0.0f, 0.0f), TrapState spre = TrapState{}) {
+  auto getv = [&](int k) {
+    if (PRE && k == (int)threadIdx.x) return vpre;
+    return make_float2(V[2 * (off + k)], V[2 * (off + k) + 1]);
+  };
   float sa = 0.0f, si = 0.0f, mx = -1.0f, mn = 3.0e38f;
   for (int k = threadIdx.x; k < M; k += NT) {
-    const float vr = V[2 * (off + k)], vi = V[2 * (off + k) + 1];
+    const float2 v = getv(k);
+    const float vr = v.x, vi = v.y;
     const float I = vr * vr + vi * vi;
     sa += sqrtf(I);
     si += I;
@@ -125,7 +132,8 @@ __device__ void update_traps(const float* __restrict__ V, const TrapState* __res
     const float mu = si / (float)M;
     float var = 0.0f, z0 = 0.0f, z1 = 0.0f, z2 = 0.0f;
     for (int k = threadIdx.x; k < M; k += NT) {
-      const float vr = V[2 * (off + k)], vi = V[2 * (off + k) + 1];
+      const float2 v = getv(k);
+      const float vr = v.x, vi = v.y;
       const float dI = vr * vr + vi * vi - mu;
       var += dI * dI;
     }
@@ -141,9 +149,10 @@ __device__ void update_traps(const float* __restrict__ V, const TrapState* __res
   if (degenerate && flag && threadIdx.x == 0) *flag = 1;
   const float floor_abs = 1e-12f * mean_abs;
   for (int k = threadIdx.x; k < M; k += NT) {
-    TrapState s = st_in[off + k];
+    TrapState s = (PRE && k == (int)threadIdx.x) ? spre : st_in[off + k];
     if (mode != 0 && !degenerate) {
-      const float vr = V[2 * (off + k)], vi = V[2 * (off + k) + 1];
+      const float2 v = getv(k);
+      const float vr = v.x, vi = v.y;
       const float amp = sqrtf(vr * vr + vi * vi);
       const bool tiny = amp < floor_abs;
       if (mode == 2) s.w *= mean_abs / (tiny ? floor_abs : amp);
@@ -554,102 +563,379 @@ k_forward_stored(const float2* __restrict__ A, const float2* __restrict__ E, con
   }
 }
 
-// ------------------------------------------------------------------ separable reformulation
+// ------------------------------------------------------------------ separable reformulation (matrix cores)
 //
 // Eq. 2 separates per trap: Delta_rev = (g U^2 + a U) + (g V^2 + b V), so
 //   e^{i 2pi Delta_j^m} = X_m(c) Y_m(r),  X_m(c) = e^{i 2pi (g U_c^2 + a U_c)},  Y_m(r) = e^{i 2pi (g V_r^2 + b V_r)}.
-// The pixel pass becomes S[r][c] = sum_m (w_m e^{i theta_m} Y_m(r)) X_m(c) (a rank-M complex
-// GEMM) and the trap pass T[r][m] = sum_c e^{i phi[r][c]} conj X_m(c) (a GEMM), then
-// V_m = (1/N) sum_r conj Y_m(r) T[r][m].  Same sums as the direct passes, with N*M
-// transcendentals replaced by (nx + ny)*M; the GEMMs run in rocBLAS (FP32 complex).
+// With the trap weights c_m = w_m e^{i theta_m} the two passes become dense complex contractions:
+//   pixel pass (Eq. 3)  S[r][c] = sum_m (c_m Y_m(r)) X_m(c),          phi = arg S
+//   trap pass (Eq. 1)   T[r][m] = sum_c e^{i phi[r][c]} conj X_m(c),  V_m = (1/N) sum_r conj Y_m(r) T[r][m]
+// of the same size as the direct sums, with the N*M transcendentals of Eq. 2 replaced by
+// per-block tables of the two factors.  Both run on the FP32 matrix cores
+// (v_mfma_f32_16x16x4_f32), each complex product as four real MFMAs.
+//
+// MFMA 16x16x4 operands: lane l = i + 16 k holds A[i][k] and B[k][i]; result D[i][j] is in
+// lane j + 16 (i / 4), register i % 4.
+//
+// A block owns 16 rows x 16 W columns of the SLM, one wave per 16 x 16 tile:
+//   pixel pass  D = X^T (columns x traps) . (c Y) (traps x rows); lane (j, g) ends with the
+//               four pixels (row0 + j, col0 + 4 g + v), v = 0..3, in its four registers
+//   epilogue    E = S / |S| = e^{i phase} of those pixels, kept in registers (and the phase,
+//               arg S, where it is wanted)
+//   trap pass   D = E (rows x columns) . conj X^T (columns x traps), the lane's four E values
+//               taken as its four k-steps (the column sum runs in that permuted order, and the
+//               B operand reads follow it), so E never leaves the registers; each lane then
+//               folds its four rows against conj Y, and the four lane groups are combined.
+// The block's tables X_m(c) (its 16 W columns) and Y_m(r), c_m Y_m(r) (its 16 rows) are
+// computed into LDS from the per-trap coefficients, trap index fastest, for super-chunks of
+// `sc` traps: (16 W + 16) sc sin/cos pairs per block, against 2 x 16 x 16 W x sc complex
+// products of the passes.  In the pixel pass lane group g takes traps base + g nk + i at
+// k-step i (i < nk), so each lane's operands are consecutive in LDS.  Every block
+// recomputes the GS/GSW update from the previous V, as the direct kernel does.
+typedef float f32x4 __attribute__((ext_vector_type(4)));
 
-// X [M][nx], conj X [M][nx] and Y [M][ny] (complex64, trap-major) for one hologram;
-// grid (ceil(max(nx,ny)/256), M).
-template <bool FRACT>
-__global__ void __launch_bounds__(256)
-k_sep_tables(const TrapCoef* __restrict__ coef, int M, int nx, int ny, float2* __restrict__ X, float2* __restrict__ Xc,
-             float2* __restrict__ Y) {
-  const int m = blockIdx.y;
-  const int i = blockIdx.x * 256 + threadIdx.x;
-  const TrapCoef c = coef[m];
-  if (i < nx) {
-    const float U = (float)(2 * i - (nx - 1));
-    const float t = to_period<FRACT>(__builtin_fmaf(c.g, U * U, c.a * U));
-    const float cs = __builtin_amdgcn_cosf(t), sn = __builtin_amdgcn_sinf(t);
-    X[(size_t)m * nx + i] = make_float2(cs, sn);
-    Xc[(size_t)m * nx + i] = make_float2(cs, -sn);
+__device__ __forceinline__ f32x4 mfma16(float a, float b, f32x4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+
+__device__ __forceinline__ float2 trap_weight(const TrapState& s) {
+  return make_float2(s.w * __builtin_amdgcn_cosf(s.theta_rev), s.w * __builtin_amdgcn_sinf(s.theta_rev));
+}
+
+__device__ __forceinline__ float2 cmul(float2 a, float2 b) {
+  return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+
+// Pixel pass operands of NK k-steps: xr -> X[column][traps], yr -> (c Y)[row][traps], NK
+// consecutive complex entries each (16-byte aligned when NK is even).
+template <int NK>
+struct PixelOps {
+  float2 x[NK], y[NK];
+  __device__ __forceinline__ void load(const float2* xr, const float2* yr) {
+    if constexpr (NK % 2 == 0) {
+#pragma unroll
+      for (int i = 0; i < NK; i += 2) {
+        const float4 a = *reinterpret_cast<const float4*>(xr + i), c = *reinterpret_cast<const float4*>(yr + i);
+        x[i] = make_float2(a.x, a.y);
+        x[i + 1] = make_float2(a.z, a.w);
+        y[i] = make_float2(c.x, c.y);
+        y[i + 1] = make_float2(c.z, c.w);
+      }
+    } else {
+#pragma unroll
+      for (int i = 0; i < NK; ++i) {
+        x[i] = xr[i];
+        y[i] = yr[i];
+      }
+    }
   }
-  if (i < ny) {
-    const float Vr = (float)(2 * i - (ny - 1));
-    const float t = to_period<FRACT>(__builtin_fmaf(c.g, Vr * Vr, c.b * Vr));
-    Y[(size_t)m * ny + i] = make_float2(__builtin_amdgcn_cosf(t), __builtin_amdgcn_sinf(t));
+  __device__ __forceinline__ void mma(f32x4& sre, f32x4& sim) const {
+#pragma unroll
+    for (int i = 0; i < NK; ++i) {
+      sre = mfma16(x[i].x, y[i].x, sre);
+      sre = mfma16(x[i].y, -y[i].y, sre);
+      sim = mfma16(x[i].x, y[i].y, sim);
+      sim = mfma16(x[i].y, y[i].x, sim);
+    }
+  }
+};
+
+template <int NK>
+__device__ __forceinline__ void pixel_tail(const float2* xr, const float2* yr, f32x4& sre, f32x4& sim) {
+  PixelOps<NK> o;
+  o.load(xr, yr);
+  o.mma(sre, sim);
+}
+
+// Sum over the four lane groups (lanes li, li + 16, li + 32, li + 48), the same value in every
+// lane: (R0 + R1) + (R2 + R3) in rows 0 and 1, (R2 + R3) + (R0 + R1) in rows 2 and 3.
+__device__ __forceinline__ float sum_lane_groups(float v) {
+  v += __shfl_xor(v, 16);
+  return v + __shfl_xor(v, 32);
+}
+
+// Trap pass for NTL consecutive tiles of 16 traps: xc -> X[column 4g][trap li] (columns xs apart),
+// yc -> Y[row 4g][trap li] (rows xs apart); tile t's trap sums over this wave's pixels go to
+// out[16 t] from the lanes of group 0.  All tiles' operands are read first and their MFMAs
+// issued back to back, so the foldings and lane-group sums overlap the products still running.
+template <int NTL>
+__device__ __forceinline__ void trap_tiles(const float2* xc, const float2* yc, int xs, const float* er,
+                                           const float* ei, int g, float2* out) {
+  float2 x[NTL][4], y[NTL][4];
+#pragma unroll
+  for (int t = 0; t < NTL; ++t) {
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      x[t][v] = xc[16 * t + v * xs];
+      y[t][v] = yc[16 * t + v * xs];
+    }
+  }
+  __builtin_amdgcn_sched_barrier(0);  // every read issued before the first MFMA waits on its own
+  f32x4 tre[NTL], tim[NTL];
+#pragma unroll
+  for (int t = 0; t < NTL; ++t) {
+    tre[t] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+    tim[t] = tre[t];
+  }
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+#pragma unroll
+    for (int t = 0; t < NTL; ++t) {
+      tre[t] = mfma16(er[v], x[t][v].x, tre[t]);
+      tre[t] = mfma16(ei[v], x[t][v].y, tre[t]);
+      tim[t] = mfma16(ei[v], x[t][v].x, tim[t]);
+      tim[t] = mfma16(er[v], -x[t][v].y, tim[t]);
+    }
+  }
+#pragma unroll
+  for (int t = 0; t < NTL; ++t) {
+    float pr = 0.0f, pi = 0.0f;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      pr = __builtin_fmaf(y[t][v].x, tre[t][v], __builtin_fmaf(y[t][v].y, tim[t][v], pr));   // Re(conj(y) t)
+      pi = __builtin_fmaf(y[t][v].x, tim[t][v], __builtin_fmaf(-y[t][v].y, tre[t][v], pi));  // Im(conj(y) t)
+    }
+    pr = sum_lane_groups(pr);
+    pi = sum_lane_groups(pi);
+    if (g == 0) out[16 * t] = make_float2(pr, pi);
   }
 }
 
-// V_m = (1/N) sum_r conj Y_m(r) T[m][r]  (T trap-major [M][ny]); one wave per trap, lanes over
-// r, fixed order.  Grid ceil(M / 4) blocks of 256.
-__global__ void __launch_bounds__(256)
-k_sep_collect(const float2* __restrict__ T, const float2* __restrict__ Y, int M, int ny, float inv_n,
-              float* __restrict__ V) {
-  const int m = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
-  if (m >= M) return;
-  float sr = 0.0f, si = 0.0f;
-  for (int r = lane; r < ny; r += 64) {
-    const float2 y = Y[(size_t)m * ny + r], t = T[(size_t)m * ny + r];
-    sr = __builtin_fmaf(y.x, t.x, __builtin_fmaf(y.y, t.y, sr));   // Re(conj(y) t)
-    si = __builtin_fmaf(y.x, t.y, __builtin_fmaf(-y.y, t.x, si));  // Im(conj(y) t)
-  }
-  sr = wave_sum(sr);
-  si = wave_sum(si);
-  if (lane == 0) {
-    V[2 * m] = sr * inv_n;
-    V[2 * m + 1] = si * inv_n;
-  }
-}
+// MODE 0: one iteration: update, pixel pass, trap-pass partials (phase written when non-null)
+// MODE 1: trap pass alone from the given phase (Eq. 1)
+// MODE 2: pixel pass alone from the given state (phase out)
+// MODE 3: adjoint of Eq. 1: weights G_m (vin), grad[j] = (1/N) Im(e^{-i phi_j} S_j) for the given phase
+// Grid (ceil(nx / 16 W), ceil(ny / 16), B); sc = traps per super-chunk (a multiple of 16);
+// dynamic LDS sep_lds_bytes(W, sc, Mmax).
+template <int W, int MODE, bool FRACT>
+__global__ void __launch_bounds__(W * 64)
+k_sep(const TrapCoef* __restrict__ coef, const HoloDesc* __restrict__ hd, const TrapState* __restrict__ st_in,
+      TrapState* __restrict__ st_out, const float* __restrict__ vin, float* __restrict__ stats, int kstat,
+      int stat_stride, int upd, int* __restrict__ flag, int nx, int ny, float inv_n, int sc,
+      float* __restrict__ phase, float* __restrict__ grad, float2* __restrict__ partial) {
+  constexpr int NT = W * 64, CW = 16 * W;
+  constexpr bool kPixel = MODE != 1, kTrap = MODE <= 1;
+  extern __shared__ float4 lds4[];
+  __shared__ float sh[8 * W];
+  const int b = blockIdx.z;
+  const int M = hd[b].m, off = hd[b].off;
+  const int Mp = (M + 15) & ~15;
+  const int XS = sc + 2;  // row stride of the table copies (float2), skewed across banks
+  float4* cf = lds4;                                     // [Mp] {a, g, b, 0}
+  float2* cw = reinterpret_cast<float2*>(cf + Mp);       // [Mp] c_m
+  float2* xt = cw + Mp;                                  // [CW][XS] X_m(c)
+  float2* yt = xt + CW * XS;                             // [16][XS] Y_m(r)
+  float2* ywt = yt + 16 * XS;                            // [16][XS] c_m Y_m(r)
+  float2* red = ywt + 16 * XS;                           // [W][sc] per-wave trap sums
 
-// Weighted rows for the next pixel pass, Yw[m][r] = w_m e^{i 2pi theta_m} Y_m(r), with the GS/GSW
-// update recomputed by every block from V (as in the fused kernel).  Grid (ceil(ny / 256), M):
-// block (x, m) handles trap m, rows 256x ..; blocks with x = 0 write st_out[m]; block (0, 0)
-// writes the figures of merit of V.  upd = 0 takes the state as is (V is not read).
-__global__ void __launch_bounds__(256)
-k_sep_weights(const float* __restrict__ V, const float2* __restrict__ Y, int M, int ny, int upd,
-              const TrapState* __restrict__ st_in, TrapState* __restrict__ st_out, float* __restrict__ stats_row,
-              int* __restrict__ flag, float2* __restrict__ Yw) {
-  __shared__ float sh[8 * 4];
-  __shared__ float2 cm;
-  const int m = blockIdx.y, x = blockIdx.x;
-  if (upd == 0) {
-    if (threadIdx.x == 0) {
-      const TrapState s = st_in[m];
-      cm = make_float2(s.w * __builtin_amdgcn_cosf(s.theta_rev), s.w * __builtin_amdgcn_sinf(s.theta_rev));
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, li = lane & 15, g = lane >> 4;
+  const int row0 = blockIdx.y * 16, cb = blockIdx.x * CW;
+  const int c0 = cb + wave * 16;
+  const int r = row0 + li;
+  const size_t pix0 = (size_t)b * nx * ny + (size_t)r * nx + c0 + 4 * g;  // pixel (r, c0 + 4 g)
+  bool in[4];
+#pragma unroll
+  for (int v = 0; v < 4; ++v) in[v] = r < ny && c0 + 4 * g + v < nx;
+  float er[4], ei[4];
+
+  // tables of traps [k0, k0 + n) into LDS: lane j keeps trap k0 + j's coefficients in registers
+  // while its wave walks the block's columns wave, wave + W, ... (tables_x) or rows wave, wave + W,
+  // ... (tables_y).  Columns past nx and rows past ny take the coordinates of the last column
+  // and row (finite entries inside the sin/cos domain; such pixels have E = 0), and traps past M
+  // are left as the formula gives them (c_m = 0, partials never written), so none of them reach
+  // V or the phase.
+  float xu[16], xu2[16], yv[16 / W], yv2[16 / W];
+#pragma unroll
+  for (int i = 0; i < 16; ++i) {
+    xu[i] = (float)(2 * min(cb + wave + i * W, nx - 1) - (nx - 1));
+    xu2[i] = xu[i] * xu[i];
+  }
+#pragma unroll
+  for (int i = 0; i < 16 / W; ++i) {
+    yv[i] = (float)(2 * min(row0 + wave + i * W, ny - 1) - (ny - 1));
+    yv2[i] = yv[i] * yv[i];
+  }
+  auto tables_x = [&](int k0, int n) {
+    for (int j = lane; j < n; j += 64) {
+      const float4 k = cf[k0 + j];
+#pragma unroll
+      for (int i = 0; i < 16; ++i) {
+        const float t = to_period<FRACT>(__builtin_fmaf(k.y, xu2[i], k.x * xu[i]));
+        xt[(wave + i * W) * XS + j] = make_float2(__builtin_amdgcn_cosf(t), __builtin_amdgcn_sinf(t));
+      }
+    }
+  };
+  auto tables_y = [&](int k0, int n, bool weighted) {
+    for (int j = lane; j < n; j += 64) {
+      const float4 k = cf[k0 + j];
+      const float2 w = weighted ? cw[k0 + j] : make_float2(0.0f, 0.0f);
+#pragma unroll
+      for (int i = 0; i < 16 / W; ++i) {
+        const float t = to_period<FRACT>(__builtin_fmaf(k.y, yv2[i], k.z * yv[i]));
+        const float2 v = make_float2(__builtin_amdgcn_cosf(t), __builtin_amdgcn_sinf(t));
+        yt[(wave + i * W) * XS + j] = v;
+        if (weighted) ywt[(wave + i * W) * XS + j] = cmul(w, v);
+      }
+    }
+  };
+  const int nsc = (Mp + sc - 1) / sc;
+
+  // per-trap coefficients into LDS.  Trap threadIdx.x's coefficients, V and state are loaded
+  // first; the block then builds the first super-chunk's X table (which needs no weights) while
+  // the update's inputs arrive, and only then does the GS/GSW update.
+  TrapCoef c_first = {0.0f, 0.0f, 0.0f, 0.0f};
+  float2 v_first = make_float2(0.0f, 0.0f);
+  TrapState s_first = {0.0f, 0.0f, 0.0f, 0.0f};
+  if ((int)threadIdx.x < M) {
+    c_first = coef[off + threadIdx.x];
+    if (kPixel && MODE != 3) {
+      s_first = st_in[off + threadIdx.x];
+      if (MODE == 0 && upd != 0) v_first = make_float2(vin[2 * (off + threadIdx.x)], vin[2 * (off + threadIdx.x) + 1]);
+    }
+  }
+  for (int m = NT + (int)threadIdx.x; m < Mp; m += NT) {
+    float4 v = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    if (m < M) {
+      const TrapCoef c = coef[off + m];
+      v = make_float4(c.a, c.g, c.b, 0.0f);
+    }
+    cf[m] = v;
+  }
+  if ((int)threadIdx.x < Mp) cf[threadIdx.x] = make_float4(c_first.a, c_first.g, c_first.b, 0.0f);
+  __syncthreads();
+  if constexpr (kPixel) {
+    tables_x(0, min(sc, Mp));
+    if (MODE == 3) {
+      for (int m = threadIdx.x; m < M; m += NT) cw[m] = make_float2(vin[2 * (off + m)], vin[2 * (off + m) + 1]);
+    } else if (MODE == 2 || upd == 0) {
+      for (int m = threadIdx.x; m < M; m += NT) cw[m] = trap_weight(m == (int)threadIdx.x ? s_first : st_in[off + m]);
+    } else {
+      const bool lead = blockIdx.x == 0 && blockIdx.y == 0;
+      auto emit = [&](int m, const TrapState& st) {
+        if (lead) st_out[off + m] = st;
+        cw[m] = trap_weight(st);
+      };
+      update_traps<NT, decltype(emit), true>(vin, st_in, off, M, upd, sh,
+                                             lead ? stats + 3 * ((size_t)b * stat_stride + kstat) : nullptr,
+                                             lead ? flag : nullptr, emit, v_first, s_first);
+    }
+    for (int m = M + (int)threadIdx.x; m < Mp; m += NT) cw[m] = make_float2(0.0f, 0.0f);
+    __syncthreads();
+  }
+
+  if constexpr (kPixel) {
+    // S^T[c][r] = sum_m X[m][c] (c_m Y[m][r])
+    f32x4 sre = {0.0f, 0.0f, 0.0f, 0.0f}, sim = sre;
+    const float2* xrow = xt + (wave * 16 + li) * XS;
+    const float2* yrow = ywt + li * XS;
+    for (int s = 0; s < nsc; ++s) {
+      const int k0 = s * sc, n = min(sc, Mp - k0);
+      if (s > 0) {
+        __syncthreads();  // the previous super-chunk is no longer read
+        tables_x(k0, n);
+      }
+      tables_y(k0, n, true);
+      __syncthreads();
+      const int ksteps = (min(n, M - k0) + 3) / 4;  // traps past M add nothing: skip them
+      const int nfull = ksteps / 8;                  // groups of 32 traps, operands double-buffered
+      PixelOps<8> ga, gb;
+      if (nfull > 0) ga.load(xrow + 8 * g, yrow + 8 * g);
+      int q = 0;
+      for (; q + 2 <= nfull; q += 2) {
+        gb.load(xrow + 32 * (q + 1) + 8 * g, yrow + 32 * (q + 1) + 8 * g);
+        __builtin_amdgcn_sched_barrier(0);
+        ga.mma(sre, sim);
+        __builtin_amdgcn_sched_barrier(0);
+        if (q + 2 < nfull) ga.load(xrow + 32 * (q + 2) + 8 * g, yrow + 32 * (q + 2) + 8 * g);
+        __builtin_amdgcn_sched_barrier(0);
+        gb.mma(sre, sim);
+        __builtin_amdgcn_sched_barrier(0);
+      }
+      if (q < nfull) ga.mma(sre, sim);
+      const int base = 32 * nfull, nk = ksteps - 8 * nfull;
+      const float2* xr = xrow + base + nk * g;
+      const float2* yr = yrow + base + nk * g;
+      switch (nk) {
+        case 1: pixel_tail<1>(xr, yr, sre, sim); break;
+        case 2: pixel_tail<2>(xr, yr, sre, sim); break;
+        case 3: pixel_tail<3>(xr, yr, sre, sim); break;
+        case 4: pixel_tail<4>(xr, yr, sre, sim); break;
+        case 5: pixel_tail<5>(xr, yr, sre, sim); break;
+        case 6: pixel_tail<6>(xr, yr, sre, sim); break;
+        case 7: pixel_tail<7>(xr, yr, sre, sim); break;
+        default: break;
+      }
+    }
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      if constexpr (MODE == 3) {
+        if (in[v]) {
+          const float pr = phase[pix0 + v] * kInv2Pi;
+          grad[pix0 + v] =
+              inv_n * (__builtin_amdgcn_cosf(pr) * sim[v] - __builtin_amdgcn_sinf(pr) * sre[v]);  // Im(e^{-i phi} S)
+        }
+      } else {
+        if (phase != nullptr && in[v]) phase[pix0 + v] = wrap_phase(atan2f(sim[v], sre[v]));
+        const float n2 = sre[v] * sre[v] + sim[v] * sim[v];
+        float cr = 1.0f, ci = 0.0f;  // arg 0 = 0
+        if (n2 >= 1.17549435e-38f) {
+          const float inv = __builtin_amdgcn_rsqf(n2);
+          cr = sre[v] * inv;
+          ci = sim[v] * inv;
+        } else if (n2 > 0.0f) {
+          const float pr = atan2f(sim[v], sre[v]) * kInv2Pi;
+          cr = __builtin_amdgcn_cosf(pr);
+          ci = __builtin_amdgcn_sinf(pr);
+        }
+        er[v] = in[v] ? cr : 0.0f;
+        ei[v] = in[v] ? ci : 0.0f;
+      }
     }
   } else {
-    const bool lead = x == 0 && m == 0;
-    update_traps<256>(V, st_in, 0, M, upd, sh, lead ? stats_row : nullptr, lead ? flag : nullptr,
-                      [&](int k, const TrapState& s) {
-                        if (k != m) return;
-                        if (x == 0) st_out[m] = s;
-                        cm = make_float2(s.w * __builtin_amdgcn_cosf(s.theta_rev), s.w * __builtin_amdgcn_sinf(s.theta_rev));
-                      });
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const float pr = in[v] ? phase[pix0 + v] * kInv2Pi : 0.0f;
+      er[v] = in[v] ? __builtin_amdgcn_cosf(pr) : 0.0f;
+      ei[v] = in[v] ? __builtin_amdgcn_sinf(pr) : 0.0f;
+    }
   }
-  __syncthreads();
-  const int r = x * 256 + threadIdx.x;
-  if (r < ny) {
-    const float2 c = cm, y = Y[(size_t)m * ny + r];
-    Yw[(size_t)m * ny + r] = make_float2(c.x * y.x - c.y * y.y, c.x * y.y + c.y * y.x);
-  }
-}
 
-// phase = arg S in [0, 2pi], E = e^{i phase} (via the FP32 phase in revolutions, as the trap pass
-// of the direct path reads it).
-__global__ void __launch_bounds__(256)
-k_sep_phase(const float2* __restrict__ S, int n, float* __restrict__ phase, float2* __restrict__ E) {
-  for (int i = blockIdx.x * 256 + threadIdx.x; i < n; i += gridDim.x * 256) {
-    const float2 s = S[i];
-    const float ph = wrap_phase(atan2f(s.y, s.x));
-    phase[i] = ph;
-    const float pr = ph * kInv2Pi;
-    E[i] = make_float2(__builtin_amdgcn_cosf(pr), __builtin_amdgcn_sinf(pr));
+  if constexpr (kTrap) {
+    // per tile of 16 traps: T^T[r][m] = sum_c E[r][c] conj X[m][c], then sum_r conj Y[m][r] T^T[r][m]
+    const int nblk = gridDim.x * gridDim.y, blk = blockIdx.y * gridDim.x + blockIdx.x;
+    const float2* xcol = xt + (wave * 16 + 4 * g) * XS + li;
+    const float2* ycol = yt + (4 * g) * XS + li;
+    for (int s = 0; s < nsc; ++s) {
+      const int k0 = s * sc, n = min(sc, Mp - k0);
+      if (!kPixel || nsc > 1) {  // one pixel-pass super-chunk is still in LDS
+        if (kPixel || s > 0) __syncthreads();
+        tables_x(k0, n);
+        tables_y(k0, n, false);
+        __syncthreads();
+      }
+      int t = 0;
+      for (; t + 128 <= n; t += 128) trap_tiles<8>(xcol + t, ycol + t, XS, er, ei, g, red + wave * sc + t + li);
+      switch ((n - t) / 16) {
+        case 1: trap_tiles<1>(xcol + t, ycol + t, XS, er, ei, g, red + wave * sc + t + li); break;
+        case 2: trap_tiles<2>(xcol + t, ycol + t, XS, er, ei, g, red + wave * sc + t + li); break;
+        case 3: trap_tiles<3>(xcol + t, ycol + t, XS, er, ei, g, red + wave * sc + t + li); break;
+        case 4: trap_tiles<4>(xcol + t, ycol + t, XS, er, ei, g, red + wave * sc + t + li); break;
+        case 5: trap_tiles<5>(xcol + t, ycol + t, XS, er, ei, g, red + wave * sc + t + li); break;
+        case 6: trap_tiles<6>(xcol + t, ycol + t, XS, er, ei, g, red + wave * sc + t + li); break;
+        case 7: trap_tiles<7>(xcol + t, ycol + t, XS, er, ei, g, red + wave * sc + t + li); break;
+        default: break;
+      }
+      __syncthreads();
+      for (int m = threadIdx.x; m < n && k0 + m < M; m += NT) {
+        float2 acc = red[m];
+#pragma unroll
+        for (int w = 1; w < W; ++w) {
+          acc.x += red[w * sc + m].x;
+          acc.y += red[w * sc + m].y;
+        }
+        partial[(size_t)(off + k0 + m) * nblk + blk] = acc;
+      }
+    }
   }
 }
 
@@ -821,32 +1107,46 @@ hipError_t launch_forward_stored(hipStream_t s, int n, int B, const float2* A, c
   return hipGetLastError();
 }
 
-hipError_t launch_sep_tables(hipStream_t s, bool fract, const TrapCoef* coef, int M, int nx, int ny, float2* X,
-                             float2* Xc, float2* Y) {
-  dim3 grid((std::max(nx, ny) + 255) / 256, M);
-  if (fract)
-    hipLaunchKernelGGL(k_sep_tables<true>, grid, dim3(256), 0, s, coef, M, nx, ny, X, Xc, Y);
-  else
-    hipLaunchKernelGGL(k_sep_tables<false>, grid, dim3(256), 0, s, coef, M, nx, ny, X, Xc, Y);
+template <int W, int MODE, bool FRACT>
+hipError_t sep_t(hipStream_t s, const SepArgs& a) {
+  // raise the kernel's dynamic LDS limit once, to everything the static part leaves
+  static const hipError_t attr = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_sep<W, MODE, FRACT>),
+                                                     hipFuncAttributeMaxDynamicSharedMemorySize, kSepLdsMax);
+  if (attr != hipSuccess) return attr;
+  const size_t lds = sep_lds_bytes(W, a.sc, a.mmax);
+  if (lds > (size_t)kSepLdsMax) return hipErrorInvalidValue;
+  dim3 grid(a.gx(), a.gy(), a.B);
+  hipLaunchKernelGGL((k_sep<W, MODE, FRACT>), grid, dim3(W * 64), lds, s, a.coef, a.hd, a.st_in, a.st_out, a.vin,
+                     a.stats, a.kstat, a.stat_stride, a.upd, a.flag, a.nx, a.ny, a.inv_n, a.sc, a.phase, a.grad,
+                     a.partial);
   return hipGetLastError();
 }
 
-hipError_t launch_sep_collect(hipStream_t s, const float2* T, const float2* Y, int M, int ny, float inv_n, float* V) {
-  hipLaunchKernelGGL(k_sep_collect, dim3((M + 3) / 4), dim3(256), 0, s, T, Y, M, ny, inv_n, V);
-  return hipGetLastError();
+template <int W, bool FRACT>
+hipError_t sep_mode(hipStream_t s, const SepArgs& a) {
+  switch (a.mode) {
+    case 0: return sep_t<W, 0, FRACT>(s, a);
+    case 1: return sep_t<W, 1, FRACT>(s, a);
+    case 2: return sep_t<W, 2, FRACT>(s, a);
+    case 3: return sep_t<W, 3, FRACT>(s, a);
+    default: return hipErrorInvalidValue;
+  }
 }
 
-hipError_t launch_sep_weights(hipStream_t s, const float* V, const float2* Y, int M, int ny, int upd,
-                              const TrapState* st_in, TrapState* st_out, float* stats_row, int* flag, float2* Yw) {
-  hipLaunchKernelGGL(k_sep_weights, dim3((ny + 255) / 256, M), dim3(256), 0, s, V, Y, M, ny, upd, st_in, st_out,
-                     stats_row, flag, Yw);
-  return hipGetLastError();
+template <int W>
+hipError_t sep_fract(hipStream_t s, const SepArgs& a) {
+  return a.fract ? sep_mode<W, true>(s, a) : sep_mode<W, false>(s, a);
 }
 
-hipError_t launch_sep_phase(hipStream_t s, const float2* S, int n, float* phase, float2* E) {
-  const int blocks = std::min((n + 255) / 256, 2048);
-  hipLaunchKernelGGL(k_sep_phase, dim3(blocks), dim3(256), 0, s, S, n, phase, E);
-  return hipGetLastError();
+hipError_t launch_sep(hipStream_t s, const SepArgs& a) {
+  if (a.W != 1 && a.W != 2 && a.W != 4) return hipErrorInvalidValue;
+  if (a.nx < 1 || a.ny < 1 || a.mmax < 1 || a.mmax > kMaxTraps || a.sc < 16 || a.sc % 16 != 0)
+    return hipErrorInvalidValue;
+  switch (a.W) {
+    case 1: return sep_fract<1>(s, a);
+    case 2: return sep_fract<2>(s, a);
+    default: return sep_fract<4>(s, a);
+  }
 }
 
 hipError_t launch_encode_u8(hipStream_t s, const float* phase, uint8_t* frame, int64_t n) {

@@ -398,14 +398,16 @@ def test_realtime_loop_warm_start_matches_oracle(hot, ctx):
         assert dt > 0
 
 
-# ------------------------------------------------------------------ separable reformulation (GEMM) variant
+# ------------------------------------------------------------------ separable reformulation (matrix-core) variant
 
 SEP_CASES = {
     "c1-256sq-16-k30": lambda: W.c1(),
     "c2-512sq-100-k50": lambda: W.c2(),
     "ragged-300x77-37-k6": lambda: W.random_problem(201, 300, 77, 37, 6),
+    "ragged-190x33-29-k6": lambda: W.random_problem(206, 190, 33, 29, 6),
     "wide-1500x6-9-k6": lambda: W.random_problem(202, 1500, 6, 9, 6),
     "tiny-3x5-1-k3": lambda: W.random_problem(204, 3, 5, 1, 3),
+    "tiny-1x1-3-k3": lambda: W.random_problem(203, 1, 1, 3, 3),
 }
 
 
@@ -419,6 +421,112 @@ def test_separable_matches_oracle(sep, name, algo):
     assert_phase(to_np(g.phase), o["phi"], frac=0.999 if p.slm.n >= 64 else 1.0)
     assert_V(to_np(g.V), o["V"])
     assert_stats(g.stats, o["stats"])
+
+
+@pytest.mark.parametrize("waves,chunk", [(1, 0), (2, 0), (4, 0), (4, 32), (2, 16), (1, 48)])
+def test_separable_every_block_width(hot, waves, chunk):
+    """Blocks of 1, 2 and 4 waves (16 x 16 W pixels), with all traps resident in LDS or streamed in
+    super-chunks of 16, 32 or 48, give the oracle's answer; the grid is ragged in both directions
+    and M = 70 leaves a partial trap tile."""
+    p = W.random_problem(430, 200, 90, 70, 5)
+    with hot.Context(0) as c:
+        c.set_variant("separable")
+        c.set_tuning(sep_waves=waves, sep_chunk=chunk)
+        g = run(c, "gsw", p)
+    o = oracle_solve("gsw", p, p.iters)
+    assert_phase(to_np(g.phase), o["phi"])
+    assert_V(to_np(g.V), o["V"])
+    assert_stats(g.stats, o["stats"])
+
+
+@pytest.mark.parametrize("algo", ["rs", "gsw"])
+def test_separable_max_traps(hot, algo):
+    """HOT_MAX_TRAPS traps with 4-wave blocks: the largest LDS footprint of the kernel."""
+    p = W.Problem(W.Slm(256, 256), W.square_grid(46, 3e-6)[:2048], W.random_phases(381, 2048), 2)
+    with hot.Context(0) as c:
+        c.set_variant("separable")
+        c.set_tuning(sep_waves=4)
+        g = run(c, algo, p, 2)
+    o = oracle_solve(algo, p, 2)
+    assert_phase(to_np(g.phase), o["phi"])
+    assert_V(to_np(g.V), o["V"])
+
+
+def test_separable_batched_equals_plain_and_oracle(sep):
+    bt = W.c4(8)
+    bt.iters = 10
+    r = sep.hot_gsw_batched(bt.slm, bt.counts, bt.xyz, bt.theta0, bt.iters)
+    torch.cuda.synchronize()
+    ph, V, st = to_np(r.phase), to_np(r.V), r.stats
+    o = bt.offsets()
+    for b in range(bt.b):
+        p = bt.problem(b)
+        g = run(sep, "gsw", p, bt.iters)
+        # (a batch may use wider blocks than a lone hologram: same sums, another order)
+        assert_phase(ph[b], to_np(g.phase), what=f"batched vs plain {b}")
+        assert_V(V[o[b]:o[b + 1]], as_complex(to_np(g.V)), what=f"batched vs plain {b}")
+        if b < 2:
+            ref = oracle.solve("gsw", p.slm, p.xyz, p.theta0, bt.iters)
+            assert_phase(ph[b], ref["phi"])
+            assert_V(V[o[b]:o[b + 1]], ref["V"])
+            assert_stats(st[b], ref["stats"])
+
+
+def test_separable_forward_V_batched_uneven(sep):
+    probs = [W.random_problem(300 + i, 200, 120, m) for i, m in enumerate((5, 64, 131))]
+    slm = probs[0].slm
+    phis = np.random.default_rng(310).uniform(0, 2 * math.pi, (3, slm.n))
+    counts = [p.m for p in probs]
+    xyz = np.concatenate([p.xyz for p in probs])
+    phase = torch.tensor(phis.reshape(3, slm.ny, slm.nx), dtype=torch.float32, device="cuda")
+    V = to_np(sep.hot_forward_V(slm, counts, xyz, phase))
+    torch.cuda.synchronize()
+    o = 0
+    for b, p in enumerate(probs):
+        ref = oracle.forward(slm, p.xyz, phis[b].astype(np.float32).astype(np.float64))
+        assert_V(V[o:o + p.m], ref, what=f"hologram {b}")
+        np.testing.assert_allclose(as_complex(V[o:o + p.m]), ref, atol=2e-6)
+        o += p.m
+
+
+@pytest.mark.parametrize("case", ["fd-64sq-4", "512sq-64"])
+def test_separable_adjoint_matches_oracle(sep, case):
+    if case == "fd-64sq-4":
+        p, phi = W.c5_fd_case()
+    else:
+        p = W.random_problem(320, 512, 512, 64)
+        phi = np.random.default_rng(321).uniform(0, 2 * math.pi, p.slm.n)
+    phi = phi.astype(np.float32).astype(np.float64)
+    G = np.random.default_rng(322).normal(size=p.m) + 1j * np.random.default_rng(323).normal(size=p.m)
+    Gt = torch.tensor(np.stack([G.real, G.imag], -1), dtype=torch.float32, device="cuda")
+    phase = torch.tensor(phi.reshape(1, p.slm.ny, p.slm.nx), dtype=torch.float32, device="cuda")
+    g = to_np(sep.hot_adjoint(p.slm, [p.m], p.xyz, phase, Gt)).ravel()
+    ref = oracle.adjoint(p.slm, p.xyz, phi, G.astype(np.complex64).astype(np.complex128))
+    rel = np.linalg.norm(g - ref) / np.linalg.norm(ref)
+    assert rel <= 1e-4, rel
+
+
+def test_separable_graph_replays_match_eager(hot):
+    p = W.c2()
+    with hot.Context(0) as eager, hot.Context(0) as graphed:
+        for c in (eager, graphed):
+            c.set_variant("separable")
+        eager.set_graphs(False)
+        ref = eager.hot_gsw(p.slm, p.xyz, p.theta0, 6, state=True)
+        torch.cuda.synchronize()
+        phase = torch.empty(p.slm.ny, p.slm.nx, device="cuda")
+        V = torch.empty(p.m, 2, device="cuda")
+        for rep in range(3):
+            r = graphed.hot_gsw(p.slm, p.xyz, p.theta0, 6, phase=phase, V=V, state=True)
+            torch.cuda.synchronize()
+            assert torch.equal(r.phase, ref.phase) and torch.equal(r.V, ref.V), rep
+            assert torch.equal(r.w, ref.w) and torch.equal(r.theta, ref.theta), rep
+            np.testing.assert_array_equal(r.stats, ref.stats)
+            junk = torch.randn(1 << 20, device="cuda").sum()
+            torch.cuda.synchronize()
+            phase.zero_()
+            V.zero_()
+            del junk
 
 
 def test_separable_1024sq_256_traps(sep):
