@@ -215,11 +215,12 @@ __device__ __forceinline__ void pad_records(float4* rec, int M) {
 // (len real entries, zero-padded to S * slen).  Each wave is split into A slices of G
 // lanes; lane (slice s, position l) owns traps l, l+G, ..., l+(TPL-1)G of a chunk and
 // loops over the pixels of its slice:
-//   t = phi - C_m - a_m U - g_m U^2  (C_m = g V^2 + b V per lane and row)   3 VALU
-//   sin t, cos t                                                             2 transcendental
-//   acc += mask (cos t, sin t)                                              2 VALU
-// The S slice partials of each trap are summed in slice order through LDS `red` and
-// written to out[m * nblk].
+//   t = phi - a_m U - g_m U^2                2 VALU
+//   sin t, cos t                             2 transcendental
+//   acc += mask (cos t, sin t)              2 VALU
+// The row-constant part of Eq. 2, C_m = g V^2 + b V, is taken out of the sum: each lane's
+// accumulator is turned by e^{-i 2pi C_m} once, after its pixels.  The S slice partials of
+// each trap are then summed in slice order through LDS `red` and written to out[m * nblk].
 template <int W, int TPL, bool FRACT>
 __device__ __forceinline__ void trap_pass_block(const TrapCoef* __restrict__ cf, int M, int G, int A, float Vr,
                                                 float V2, const float4* px, int len, float2* red,
@@ -241,7 +242,7 @@ __device__ __forceinline__ void trap_pass_block(const TrapCoef* __restrict__ cf,
       if (m < M) c = cf[m];
       na[k] = -c.a;
       ng[k] = -c.g;
-      cc[k] = __builtin_fmaf(c.g, V2, c.b * Vr);
+      cc[k] = to_period<FRACT>(__builtin_fmaf(c.g, V2, c.b * Vr));
       accr[k] = 0.0f;
       acci[k] = 0.0f;
     }
@@ -250,10 +251,17 @@ __device__ __forceinline__ void trap_pass_block(const TrapCoef* __restrict__ cf,
       const float4 p = mine[j];
 #pragma unroll
       for (int k = 0; k < TPL; ++k) {
-        const float t = to_period<FRACT>(__builtin_fmaf(ng[k], p.z, __builtin_fmaf(na[k], p.y, p.x - cc[k])));
+        const float t = to_period<FRACT>(__builtin_fmaf(ng[k], p.z, __builtin_fmaf(na[k], p.y, p.x)));
         accr[k] = __builtin_fmaf(p.w, __builtin_amdgcn_cosf(t), accr[k]);
         acci[k] = __builtin_fmaf(p.w, __builtin_amdgcn_sinf(t), acci[k]);
       }
+    }
+#pragma unroll
+    for (int k = 0; k < TPL; ++k) {  // acc *= e^{-i 2pi C}
+      const float cs = __builtin_amdgcn_cosf(cc[k]), sn = __builtin_amdgcn_sinf(cc[k]);
+      const float re = __builtin_fmaf(accr[k], cs, acci[k] * sn);
+      acci[k] = __builtin_fmaf(acci[k], cs, -accr[k] * sn);
+      accr[k] = re;
     }
     __syncthreads();  // red[] is free: earlier readers (previous chunk, or the pixel pass) are done
     if (active) {
@@ -656,8 +664,8 @@ __device__ __forceinline__ float sum_lane_groups(float v) {
 
 // Trap pass for NTL consecutive tiles of 16 traps: xc -> X[column 4g][trap li] (columns xs apart),
 // yc -> Y[row 4g][trap li] (rows xs apart); tile t's trap sums over this wave's pixels go to
-// out[16 t] from the lanes of group 0.  All tiles' operands are read first and their MFMAs
-// issued back to back, so the foldings and lane-group sums overlap the products still running.
+// out[16 t] from the lanes of group 0.  The tiles' MFMAs are interleaved, so one tile's folding
+// and lane-group sums overlap the products of the others.
 template <int NTL>
 __device__ __forceinline__ void trap_tiles(const float2* xc, const float2* yc, int xs, const float* er,
                                            const float* ei, int g, float2* out) {
@@ -670,7 +678,6 @@ __device__ __forceinline__ void trap_tiles(const float2* xc, const float2* yc, i
       y[t][v] = yc[16 * t + v * xs];
     }
   }
-  __builtin_amdgcn_sched_barrier(0);  // every read issued before the first MFMA waits on its own
   f32x4 tre[NTL], tim[NTL];
 #pragma unroll
   for (int t = 0; t < NTL; ++t) {
