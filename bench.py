@@ -99,7 +99,10 @@ def main():
         main_ctx = hot.Context(0)
         tr = autotune.tune(main_ctx, p.slm, p.xyz, p.theta0, cache=None, reps=20)
         table = tr["table"]
-        default = next(r for r in table if r["pixels_per_lane"] == 1 and r["segment"] == 0 and r["traps_per_lane"] == 0)
+        main_ctx.set_tuning()  # the library's own choice of every knob, for comparison
+        pd = main_ctx.hot_time_passes(p.slm, p.xyz, p.theta0, reps=20)
+        main_ctx.set_tuning(**tr["knobs"])
+        default = {"iteration_us": round(float(pd[0]) * 1e3, 3), "reduce_us": round(float(pd[1]) * 1e3, 3)}
         tuning = {"knobs": tr["knobs"], "best": table[0], "library_default": default, "worst": table[-1],
                   "configurations": len(table)}
         log(f"[bench] autotuned {tr['knobs']}: {table[0]['iteration_us']} us vs default {default['iteration_us']} us")

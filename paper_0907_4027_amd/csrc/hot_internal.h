@@ -60,6 +60,7 @@ struct IterArgs {
   FwdGeom fg;
   int B = 1;
   int nt = 256, q = 1, tpl = 1;  // block threads (256/512), pixels per lane (1/2), traps per lane
+  int m_one = 0;                 // B == 1: the trap count (the kernel then skips the descriptor for M)
   bool fract = false;
   const TrapCoef* coef = nullptr;
   const HoloDesc* hd = nullptr;

@@ -70,6 +70,31 @@ __device__ __forceinline__ float wave_min(float v) {
 
 __device__ __forceinline__ float wrap_phase(float ph) { return ph < 0.0f ? ph + kTwoPi : ph; }
 
+// arg(x + i y) in [0, 2pi] (arg 0 = 0).  The octant is folded onto t = min(|x|,|y|) / max(|x|,|y|)
+// in [0, 1], where atan t = t P(t^2) with P of degree 7: coefficients from a Lawson-weighted
+// least-squares (near-minimax) fit to atan on [0, 1], max error 4e-8 in exact arithmetic and
+// 1.4e-7 rad evaluated in FP32; the reciprocal adds at most 1.2e-7.  Then the octant and the
+// quadrant are undone.
+__device__ __forceinline__ float phase_of(float y, float x) {
+  const float ax = __builtin_fabsf(x), ay = __builtin_fabsf(y);
+  const float mx = __builtin_fmaxf(ax, ay), mn = __builtin_fminf(ax, ay);
+  const float t = mx > 0.0f ? mn * __builtin_amdgcn_rcpf(mx) : 0.0f;
+  const float s = t * t;
+  float p = -4.054570390e-03f;
+  p = __builtin_fmaf(p, s, 2.186296944e-02f);
+  p = __builtin_fmaf(p, s, -5.591234356e-02f);
+  p = __builtin_fmaf(p, s, 9.642198569e-02f);
+  p = __builtin_fmaf(p, s, -1.390863004e-01f);
+  p = __builtin_fmaf(p, s, 1.994656575e-01f);
+  p = __builtin_fmaf(p, s, -3.332986079e-01f);
+  p = __builtin_fmaf(p, s, 9.999993356e-01f);
+  float r = p * t;
+  if (ay > ax) r = 1.57079632679489662f - r;
+  if (x < 0.0f) r = 3.14159265358979324f - r;
+  if (y < 0.0f) r = kTwoPi - r;
+  return r;
+}
+
 // Block-wide (NT threads) sums of a and b, max of c, min of d; every thread gets the
 // results.  Waves reduce with wave_sum/max/min, lane 0 of each wave publishes to `sh`
 // (4 * (NT / 64) floats, not reused by the caller), one barrier, then every thread combines
@@ -246,15 +271,23 @@ __device__ __forceinline__ void trap_pass_block(const TrapCoef* __restrict__ cf,
       accr[k] = 0.0f;
       acci[k] = 0.0f;
     }
-#pragma unroll 2
-    for (int j = 0; j < slen; ++j) {
-      const float4 p = mine[j];
+    // two pixels per step; the next two are read while these are summed (the reads stay inside
+    // px, which holds S * slen + 3 entries; a pixel past an odd slice end gets mask 0)
+    float4 pa = mine[0], pb = mine[1];
+    for (int j = 0; j < slen; j += 2) {
+      const float4 pc = mine[j + 2], pd = mine[j + 3];
+      if (j + 1 >= slen) pb.w = 0.0f;
 #pragma unroll
       for (int k = 0; k < TPL; ++k) {
-        const float t = to_period<FRACT>(__builtin_fmaf(ng[k], p.z, __builtin_fmaf(na[k], p.y, p.x)));
-        accr[k] = __builtin_fmaf(p.w, __builtin_amdgcn_cosf(t), accr[k]);
-        acci[k] = __builtin_fmaf(p.w, __builtin_amdgcn_sinf(t), acci[k]);
+        const float ta = to_period<FRACT>(__builtin_fmaf(ng[k], pa.z, __builtin_fmaf(na[k], pa.y, pa.x)));
+        const float tb = to_period<FRACT>(__builtin_fmaf(ng[k], pb.z, __builtin_fmaf(na[k], pb.y, pb.x)));
+        accr[k] = __builtin_fmaf(pa.w, __builtin_amdgcn_cosf(ta), accr[k]);
+        acci[k] = __builtin_fmaf(pa.w, __builtin_amdgcn_sinf(ta), acci[k]);
+        accr[k] = __builtin_fmaf(pb.w, __builtin_amdgcn_cosf(tb), accr[k]);
+        acci[k] = __builtin_fmaf(pb.w, __builtin_amdgcn_sinf(tb), acci[k]);
       }
+      pa = pc;
+      pb = pd;
     }
 #pragma unroll
     for (int k = 0; k < TPL; ++k) {  // acc *= e^{-i 2pi C}
@@ -290,15 +323,17 @@ __device__ __forceinline__ void trap_pass_block(const TrapCoef* __restrict__ cf,
 //   upd = 0: use st_in as is;  1/2: GS/GSW update from Vprev and st_in, recomputed by every
 //   block; block (0, 0, b) also writes the new state to st_out and the figures of merit of
 //   Vprev to stats[b][kstat].
+//   m_one > 0: a single hologram of m_one traps (offset 0), so the update's loads need not
+//   wait for the descriptor.
 // Writes phase (radians) and the trap-pass partials of the new mask.
 template <int NT, int Q, int TPL, bool FRACT>
 __global__ void __launch_bounds__(NT)
 k_iter(const TrapCoef* __restrict__ coef, const HoloDesc* __restrict__ hd, const TrapState* __restrict__ st_in,
        TrapState* __restrict__ st_out, const float* __restrict__ Vprev, float* __restrict__ stats, int kstat,
-       int stat_stride, int upd, int* __restrict__ flag, int nx, int ny, int seg_w, int nseg,
+       int stat_stride, int upd, int* __restrict__ flag, int nx, int ny, int seg_w, int nseg, int m_one,
        float* __restrict__ phase, float2* __restrict__ partial) {
   constexpr int W = NT / 64;
-  constexpr int PXN = NT * Q + 64;
+  constexpr int PXN = NT * Q + 136;  // slices cover < len + S <= len + 128 entries, plus 3 read ahead
   constexpr int REDN = W * 64 * TPL;                   // float2 slice partials
   constexpr int RECN = rec_pad(kMaxTraps);             // float4 pixel-pass records
   constexpr int UN = 2 * RECN > REDN ? 2 * RECN : REDN;  // in float2 units
@@ -306,7 +341,7 @@ k_iter(const TrapCoef* __restrict__ coef, const HoloDesc* __restrict__ hd, const
   __shared__ float2 ubuf[UN];  // pixel-pass records, then slice partials in the trap pass
   __shared__ float sh[8 * W];
   const int b = blockIdx.z, r = blockIdx.y, sg = blockIdx.x;
-  const int M = hd[b].m, off = hd[b].off, G = hd[b].g, A = hd[b].a;
+  const int M = m_one > 0 ? m_one : hd[b].m, off = m_one > 0 ? 0 : hd[b].off;
   const TrapCoef* __restrict__ cf = coef + off;
   const float Vr = (float)(2 * r - (ny - 1));
   const float V2 = Vr * Vr;
@@ -344,7 +379,7 @@ k_iter(const TrapCoef* __restrict__ coef, const HoloDesc* __restrict__ hd, const
   for (int q = 0; q < Q; ++q) {
     const int i = threadIdx.x + q * NT;
     if (i < len) {
-      const float ph = wrap_phase(atan2f(si[q], sr[q]));
+      const float ph = phase_of(si[q], sr[q]);
       prow[i] = ph;
       px[i] = make_float4(ph * kInv2Pi, U[q], U2[q], 1.0f);
     } else {
@@ -354,8 +389,8 @@ k_iter(const TrapCoef* __restrict__ coef, const HoloDesc* __restrict__ hd, const
   for (int i = NT * Q + threadIdx.x; i < PXN; i += NT) px[i] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
   __syncthreads();
   const int nblk = ny * nseg;
-  trap_pass_block<W, TPL, FRACT>(cf, M, G, A, Vr, V2, px, len, ubuf, partial + (size_t)off * nblk + r * nseg + sg,
-                                 nblk);
+  trap_pass_block<W, TPL, FRACT>(cf, M, hd[b].g, hd[b].a, Vr, V2, px, len, ubuf,
+                                 partial + (size_t)off * nblk + r * nseg + sg, nblk);
 }
 
 // ------------------------------------------------------------------ stand-alone passes
@@ -405,7 +440,7 @@ k_backward(const TrapCoef* __restrict__ coef, const TrapState* __restrict__ st, 
     const int c = cbase + q * kBlock;
     if (c < nx) {
       if constexpr (MODE == 0) {
-        phase[rowbase + c] = wrap_phase(atan2f(si[q], sr[q]));
+        phase[rowbase + c] = phase_of(si[q], sr[q]);
       } else {
         float sp, cp;
         sincosf(phase[rowbase + c], &sp, &cp);
@@ -421,14 +456,14 @@ __global__ void __launch_bounds__(kBlock)
 k_forward(const TrapCoef* __restrict__ coef, const HoloDesc* __restrict__ hd, const float* __restrict__ phase,
           int nx, int ny, int seg_w, int nseg, float2* __restrict__ partial) {
   constexpr int W = kBlock / 64;
-  __shared__ float4 px[kSegMax + 64];
+  __shared__ float4 px[kSegMax + 72];  // slices cover < len + S <= len + 64 entries, plus 3 read ahead
   __shared__ float2 red[W * 64 * TPL];
   const int b = blockIdx.z, r = blockIdx.y, sg = blockIdx.x;
   const int M = hd[b].m, G = hd[b].g, A = hd[b].a, off = hd[b].off;
   const int cbeg = sg * seg_w;
   const int len = min(nx, cbeg + seg_w) - cbeg;
   const int S = W * A;
-  const int padded = S * ((len + S - 1) / S);
+  const int padded = S * ((len + S - 1) / S) + 4;  // zeros past the last slice for the read-ahead
   const float* __restrict__ ph = phase + (size_t)b * nx * ny + (size_t)r * nx + cbeg;
   for (int i = threadIdx.x; i < padded; i += kBlock) {
     if (i < len) {
@@ -528,7 +563,7 @@ k_backward_stored(const float2* __restrict__ A, const TrapState* __restrict__ st
     sr = __builtin_fmaf(k.x, v.x, __builtin_fmaf(-k.y, v.y, sr));
     si = __builtin_fmaf(k.x, v.y, __builtin_fmaf(k.y, v.x, si));
   }
-  const float ph = wrap_phase(atan2f(si, sr));
+  const float ph = phase_of(si, sr);
   phase[(size_t)b * n + j] = ph;
   const float pr = ph * kInv2Pi;
   E[(size_t)b * n + j] = make_float2(__builtin_amdgcn_cosf(pr), __builtin_amdgcn_sinf(pr));
@@ -882,7 +917,7 @@ k_sep(const TrapCoef* __restrict__ coef, const HoloDesc* __restrict__ hd, const 
               inv_n * (__builtin_amdgcn_cosf(pr) * sim[v] - __builtin_amdgcn_sinf(pr) * sre[v]);  // Im(e^{-i phi} S)
         }
       } else {
-        if (phase != nullptr && in[v]) phase[pix0 + v] = wrap_phase(atan2f(sim[v], sre[v]));
+        if (phase != nullptr && in[v]) phase[pix0 + v] = phase_of(sim[v], sre[v]);
         const float n2 = sre[v] * sre[v] + sim[v] * sim[v];
         float cr = 1.0f, ci = 0.0f;  // arg 0 = 0
         if (n2 >= 1.17549435e-38f) {
@@ -983,8 +1018,8 @@ hipError_t iter_t(hipStream_t s, const IterArgs& a) {
   if (a.fg.seg_w > NT * Q) return hipErrorInvalidValue;
   dim3 grid(a.fg.nseg, a.fg.ny, a.B);
   hipLaunchKernelGGL((k_iter<NT, Q, TPL, FRACT>), grid, dim3(NT), 0, s, a.coef, a.hd, a.st_in, a.st_out, a.Vprev,
-                     a.stats, a.kstat, a.stat_stride, a.upd, a.flag, a.fg.nx, a.fg.ny, a.fg.seg_w, a.fg.nseg, a.phase,
-                     a.partial);
+                     a.stats, a.kstat, a.stat_stride, a.upd, a.flag, a.fg.nx, a.fg.ny, a.fg.seg_w, a.fg.nseg,
+                     a.B == 1 ? a.m_one : 0, a.phase, a.partial);
   return hipGetLastError();
 }
 
