@@ -40,6 +40,25 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+def measured_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed counter summary, or None once the kernel
+    source has changed since the counters were taken (the summary records its SHA-256)."""
+    import hashlib
+    import re
+    path = os.path.join(ROOT, "profiles", f"{kernel}_traffic_gsw-512sq-100traps.md")
+    src = os.path.join(ROOT, "paper_0907_4027_amd", "csrc", "hot_kernels.hip")
+    if not os.path.exists(path):
+        return None
+    text = open(path).read()
+    m_sha = re.search(r"kernel source sha256: ([0-9a-f]{64})", text)
+    m_b = re.search(r"HBM bytes per launch: ([0-9.eE+]+)", text)
+    if not m_sha or not m_b:
+        return None
+    if hashlib.sha256(open(src, "rb").read()).hexdigest() != m_sha.group(1):
+        return None
+    return float(m_b.group(1))
+
+
 def time_calls(fn, reps, sync):
     import torch
     sync()
@@ -59,8 +78,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-extra", action="store_true", help="skip batched / adjoint / stored comparisons")
-    ap.add_argument("--no-tune", action="store_true", help="keep the library's built-in launch shapes")
-    ap.add_argument("--only", choices=["main", "passes", "batched", "adjoint", "stored", "interactive", "separable", "fig7"], default=None,
+    ap.add_argument("--no-tune", action="store_true", help="skip the autotuner's launch-shape sweep")
+    ap.add_argument("--only", choices=["main", "passes", "tune", "batched", "adjoint", "stored", "interactive", "separable",
+                                       "fig7", "counters"], default=None,
                     help="run one section only (for profiler runs)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -93,19 +113,21 @@ def main():
 
     ms = None
     tuning = None
-    main_ctx = ctx  # the tuned launch shape applies to the headline problem only
-    if args.only in (None, "main", "passes") and not args.no_tune:
+    main_ctx = ctx  # the headline runs the library's own launch shape
+    if args.only in (None, "tune") and not args.no_tune:
+        # ablation: the autotuner's sweep of the launch-shape knobs on its own context; the headline
+        # keeps the library's choice so that profiles and counters describe the same kernel
         from paper_0907_4027_amd import autotune
-        main_ctx = hot.Context(0)
-        tr = autotune.tune(main_ctx, p.slm, p.xyz, p.theta0, cache=None, reps=20)
+        with hot.Context(0) as tctx:
+            tr = autotune.tune(tctx, p.slm, p.xyz, p.theta0, cache=None, reps=20, apply=False)
+            pd = tctx.hot_time_passes(p.slm, p.xyz, p.theta0, reps=20)
         table = tr["table"]
-        main_ctx.set_tuning()  # the library's own choice of every knob, for comparison
-        pd = main_ctx.hot_time_passes(p.slm, p.xyz, p.theta0, reps=20)
-        main_ctx.set_tuning(**tr["knobs"])
         default = {"iteration_us": round(float(pd[0]) * 1e3, 3), "reduce_us": round(float(pd[1]) * 1e3, 3)}
-        tuning = {"knobs": tr["knobs"], "best": table[0], "library_default": default, "worst": table[-1],
-                  "configurations": len(table)}
-        log(f"[bench] autotuned {tr['knobs']}: {table[0]['iteration_us']} us vs default {default['iteration_us']} us")
+        tuning = {"best_knobs": tr["knobs"], "best": table[0], "library_default": default, "worst": table[-1],
+                  "configurations": len(table),
+                  "best_vs_default": round(default["iteration_us"] / table[0]["iteration_us"], 4)}
+        log(f"[bench] autotune sweep: best {tr['knobs']} {table[0]['iteration_us']} us, library default "
+            f"{default['iteration_us']} us, worst {table[-1]['iteration_us']} us over {len(table)} shapes")
     if args.only in (None, "main"):
         for _ in range(args.warmup):
             step()
@@ -118,9 +140,20 @@ def main():
         st = main_ctx.hot_gsw(p.slm, p.xyz, p.theta0, K, phase=phase, V=V, stats=True).stats
         log(f"[bench] final e={st[-1, 0]:.4f} u={st[-1, 1]:.4f} sigma={st[-1, 2]:.4f}")
 
+    # ---------------------------------------------------------------- hardware-counter runs
+    if args.only == "counters":
+        # a plain device-to-device copy of known size (FETCH_SIZE / WRITE_SIZE calibration), then the
+        # pass-timing launches of the headline kernel
+        src = torch.ones(64 << 20, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        sync()
+        log(f"[bench] counters: 3 copies of {src.numel() * 4 >> 20} MiB")
+
     # ---------------------------------------------------------------- per-pass timings -> roofline
     roof = None
-    if args.only in (None, "main", "passes"):
+    if args.only in (None, "main", "passes", "counters"):
         pm = main_ctx.hot_time_passes(p.slm, p.xyz, p.theta0, reps=50)
         terms = N * M
         log(f"[bench] ms/launch: iteration kernel {pm[0]:.4f}  reduce {pm[1]:.4f}  "
@@ -130,7 +163,8 @@ def main():
         peak = PEAK_TERMS_PER_S / 1e9
         roof = {"bound": "alu", "kernel": "k_iter (GSW update + pixel pass + trap pass, fused)",
                 "achieved": round(achieved, 1), "peak": round(peak, 1), "unit": "Gterm/s",
-                "frac": round(achieved / peak, 4), "traffic": None,
+                "frac": round(achieved / peak, 4), "traffic": measured_traffic("k_iter"),
+                "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
                 "ms_per_launch": {"iteration": round(float(pm[0]), 5), "reduce": round(float(pm[1]), 5),
                                   "pixel_pass_alone": round(float(pm[2]), 5), "trap_pass_alone": round(float(pm[3]), 5)},
                 "frac_pixel_pass_alone": round(terms / (pm[2] * 1e-3) / PEAK_TERMS_PER_S, 4),
@@ -311,13 +345,13 @@ def main():
         return
     value = N * M * K / (ms * 1e-3)
     line = {
-        "metric": "pixel-trap updates/s, GSW 512^2 x 100 3D traps; batched & adjoint vs plain",
-        "value": value, "unit": "pixel-trap updates/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "metric": "pixel\u00b7trap updates/s, GSW 512\u00b2\u00d7100 3D traps; batched & adjoint vs plain",
+        "value": value, "unit": "pixel\u00b7trap updates/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": ms, "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
         "data": "synthetic (seeded trap arrays, workloads.c2)",
         "config": {"workload": "gsw-512sq-100traps", "nx": 512, "ny": 512, "traps": M, "iterations": K,
                    "algorithm": "GSW", "variant": "on-the-fly Delta", "parallelism": "single GPU",
-                   "launch_shape": tuning["knobs"] if tuning else "library default"},
+                   "launch_shape": "library default"},
         "holograms_per_s": 1e3 / ms,
         "roofline": roof, "cpu_baseline": cpu, "tuning": tuning, **out,
     }

@@ -256,7 +256,9 @@ int prepare(hot_ctx* c, const hot_slm* slm, int B, const int32_t* counts, const 
     int segmax = 512 * q;
     if (c->tune_seg > 0) segmax = std::min(segmax, c->tune_seg);
     P.fg = row_segments(slm->nx, slm->ny, segmax);
-    P.q = (c->tune_q == 0 && P.fg.seg_w > 512) ? 2 : q;
+    // two pixels per lane once a segment outgrows 256 pixels (measured faster than one pixel on
+    // 512-thread blocks: the pixel pass reuses each trap record twice)
+    P.q = (c->tune_q == 0 && P.fg.seg_w > 256) ? 2 : q;
     P.nt = P.fg.seg_w <= 256 * P.q ? 256 : 512;
   }
   P.fgf = row_segments(slm->nx, slm->ny, c->tune_seg > 0 ? c->tune_seg : kSegMax);
