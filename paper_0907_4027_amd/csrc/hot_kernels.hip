@@ -202,26 +202,52 @@ constexpr int kTrapChunk = 4;
 __host__ __device__ constexpr int rec_pad(int m) { return (m + 2 * kTrapChunk - 1) / kTrapChunk * kTrapChunk; }
 
 template <int Q, bool FRACT>
+__device__ __forceinline__ void pixel_chunk(const float4* c, const float* U, const float* U2, float* sr, float* si) {
+#pragma unroll
+  for (int i = 0; i < kTrapChunk; ++i) {
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+      const float t = to_period<FRACT>(__builtin_fmaf(c[i].y, U2[q], __builtin_fmaf(c[i].x, U[q], c[i].z)));
+      const float sn = __builtin_amdgcn_sinf(t), cs = __builtin_amdgcn_cosf(t);
+      sr[q] = __builtin_fmaf(c[i].w, cs, sr[q]);
+      si[q] = __builtin_fmaf(c[i].w, sn, si[q]);
+    }
+  }
+}
+
+// Two record buffers alternate: one chunk is summed while the next one is read.  The offset of
+// each read is hidden from the optimiser (an empty asm on the uniform counter); otherwise it
+// proves that a chunk equals the one read a step earlier and reloads it where it is used,
+// waiting on LDS each step.  Full double steps run while 8 traps remain, then at most two
+// chunks.  Every read stays below rec_pad(M) (the loop reads up to m0 + 11 with m0 + 8 <= M).
+template <int Q, bool FRACT>
 __device__ __forceinline__ void pixel_terms(const float4* rec, int M, const float* U, const float* U2, float* sr,
                                             float* si) {
-  float4 cur[kTrapChunk], nxt[kTrapChunk];
+  float4 ra[kTrapChunk], rb[kTrapChunk];
 #pragma unroll
-  for (int i = 0; i < kTrapChunk; ++i) cur[i] = rec[i];
-  for (int m0 = 0; m0 < M; m0 += kTrapChunk) {
+  for (int i = 0; i < kTrapChunk; ++i) ra[i] = rec[i];
+  int m0 = 0;
+  for (; m0 + 2 * kTrapChunk <= M; m0 += 2 * kTrapChunk) {
+    int nb = m0 + kTrapChunk;
+    asm volatile("" : "+s"(nb));
 #pragma unroll
-    for (int i = 0; i < kTrapChunk; ++i) nxt[i] = rec[m0 + kTrapChunk + i];
+    for (int i = 0; i < kTrapChunk; ++i) rb[i] = rec[nb + i];
+    __builtin_amdgcn_sched_barrier(0);
+    pixel_chunk<Q, FRACT>(ra, U, U2, sr, si);
+    int na = m0 + 2 * kTrapChunk;
+    asm volatile("" : "+s"(na));
 #pragma unroll
-    for (int i = 0; i < kTrapChunk; ++i) {
+    for (int i = 0; i < kTrapChunk; ++i) ra[i] = rec[na + i];
+    __builtin_amdgcn_sched_barrier(0);
+    pixel_chunk<Q, FRACT>(rb, U, U2, sr, si);
+  }
+  if (m0 < M) {
+    if (m0 + kTrapChunk < M) {
 #pragma unroll
-      for (int q = 0; q < Q; ++q) {
-        const float t = to_period<FRACT>(__builtin_fmaf(cur[i].y, U2[q], __builtin_fmaf(cur[i].x, U[q], cur[i].z)));
-        const float sn = __builtin_amdgcn_sinf(t), cs = __builtin_amdgcn_cosf(t);
-        sr[q] = __builtin_fmaf(cur[i].w, cs, sr[q]);
-        si[q] = __builtin_fmaf(cur[i].w, sn, si[q]);
-      }
+      for (int i = 0; i < kTrapChunk; ++i) rb[i] = rec[m0 + kTrapChunk + i];
     }
-#pragma unroll
-    for (int i = 0; i < kTrapChunk; ++i) cur[i] = nxt[i];
+    pixel_chunk<Q, FRACT>(ra, U, U2, sr, si);
+    if (m0 + kTrapChunk < M) pixel_chunk<Q, FRACT>(rb, U, U2, sr, si);
   }
 }
 
@@ -246,10 +272,36 @@ __device__ __forceinline__ void pad_records(float4* rec, int M) {
 // The row-constant part of Eq. 2, C_m = g V^2 + b V, is taken out of the sum: each lane's
 // accumulator is turned by e^{-i 2pi C_m} once, after its pixels.  The S slice partials of
 // each trap are then summed in slice order through LDS `red` and written to out[m * nblk].
+// The coefficients one trap-pass lane needs for the traps it owns in one chunk: -a, -g and the
+// row constant C_m = g V^2 + b V (revolutions).  Traps past M get zeros (their sums are unused).
+template <int TPL>
+struct LaneCoef {
+  float na[TPL], ng[TPL], cc[TPL];
+};
+template <int TPL>
+__device__ __forceinline__ LaneCoef<TPL> load_lane_coef(const TrapCoef* __restrict__ cf, int M, int G, int k0,
+                                                        float Vr, float V2) {
+  const int lane = threadIdx.x & 63;
+  const int tl = lane - lane / G * G;
+  LaneCoef<TPL> lc;
+#pragma unroll
+  for (int k = 0; k < TPL; ++k) {
+    const int m = k0 + tl + k * G;
+    TrapCoef c = {0.0f, 0.0f, 0.0f, 0.0f};
+    if (m < M) c = cf[m];
+    lc.na[k] = -c.a;
+    lc.ng[k] = -c.g;
+    lc.cc[k] = __builtin_fmaf(c.g, V2, c.b * Vr);
+  }
+  return lc;
+}
+
+// `first` holds the lane's coefficients of the first chunk (k0 = 0), loaded by the caller before
+// its own global stores, so that waiting for them does not wait for those stores too.
 template <int W, int TPL, bool FRACT>
 __device__ __forceinline__ void trap_pass_block(const TrapCoef* __restrict__ cf, int M, int G, int A, float Vr,
                                                 float V2, const float4* px, int len, float2* red,
-                                                float2* __restrict__ out, int nblk) {
+                                                float2* __restrict__ out, int nblk, const LaneCoef<TPL>& first) {
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int s = lane / G, tl = lane - s * G;
   const bool active = s < A;
@@ -259,35 +311,59 @@ __device__ __forceinline__ void trap_pass_block(const TrapCoef* __restrict__ cf,
   const float4* mine = px + sidx * slen;
   const int nslot = G * TPL;
   for (int k0 = 0; k0 < M; k0 += nslot) {
+    const LaneCoef<TPL> lc = k0 == 0 ? first : load_lane_coef<TPL>(cf, M, G, k0, Vr, V2);
     float na[TPL], ng[TPL], cc[TPL], accr[TPL], acci[TPL];
 #pragma unroll
     for (int k = 0; k < TPL; ++k) {
-      const int m = k0 + tl + k * G;
-      TrapCoef c = {0.0f, 0.0f, 0.0f, 0.0f};
-      if (m < M) c = cf[m];
-      na[k] = -c.a;
-      ng[k] = -c.g;
-      cc[k] = to_period<FRACT>(__builtin_fmaf(c.g, V2, c.b * Vr));
+      na[k] = lc.na[k];
+      ng[k] = lc.ng[k];
+      cc[k] = to_period<FRACT>(lc.cc[k]);
       accr[k] = 0.0f;
       acci[k] = 0.0f;
     }
-    // two pixels per step; the next two are read while these are summed (the reads stay inside
-    // px, which holds S * slen + 3 entries; a pixel past an odd slice end gets mask 0)
-    float4 pa = mine[0], pb = mine[1];
-    for (int j = 0; j < slen; j += 2) {
-      const float4 pc = mine[j + 2], pd = mine[j + 3];
-      if (j + 1 >= slen) pb.w = 0.0f;
+    // Two pixels per half step, from two register pairs that alternate: one pair is summed while
+    // the next is read (offsets hidden from the optimiser as in the pixel pass).  Full double
+    // steps run while 4 pixels remain, then at most 3.  Reads reach at most mine[slen + 1],
+    // inside px (S * slen + 3 entries); the pixel past an odd slice end gets mask 0.
+    auto terms = [&](const float4& p0, const float4& p1) {
 #pragma unroll
       for (int k = 0; k < TPL; ++k) {
-        const float ta = to_period<FRACT>(__builtin_fmaf(ng[k], pa.z, __builtin_fmaf(na[k], pa.y, pa.x)));
-        const float tb = to_period<FRACT>(__builtin_fmaf(ng[k], pb.z, __builtin_fmaf(na[k], pb.y, pb.x)));
-        accr[k] = __builtin_fmaf(pa.w, __builtin_amdgcn_cosf(ta), accr[k]);
-        acci[k] = __builtin_fmaf(pa.w, __builtin_amdgcn_sinf(ta), acci[k]);
-        accr[k] = __builtin_fmaf(pb.w, __builtin_amdgcn_cosf(tb), accr[k]);
-        acci[k] = __builtin_fmaf(pb.w, __builtin_amdgcn_sinf(tb), acci[k]);
+        const float ta = to_period<FRACT>(__builtin_fmaf(ng[k], p0.z, __builtin_fmaf(na[k], p0.y, p0.x)));
+        const float tb = to_period<FRACT>(__builtin_fmaf(ng[k], p1.z, __builtin_fmaf(na[k], p1.y, p1.x)));
+        accr[k] = __builtin_fmaf(p0.w, __builtin_amdgcn_cosf(ta), accr[k]);
+        acci[k] = __builtin_fmaf(p0.w, __builtin_amdgcn_sinf(ta), acci[k]);
+        accr[k] = __builtin_fmaf(p1.w, __builtin_amdgcn_cosf(tb), accr[k]);
+        acci[k] = __builtin_fmaf(p1.w, __builtin_amdgcn_sinf(tb), acci[k]);
       }
-      pa = pc;
-      pb = pd;
+    };
+    float4 pa = mine[0], pb = mine[1], pc, pd;
+    int j = 0;
+    for (; j + 4 <= slen; j += 4) {
+      int nc = j + 2;
+      asm volatile("" : "+s"(nc));
+      pc = mine[nc];
+      pd = mine[nc + 1];
+      __builtin_amdgcn_sched_barrier(0);
+      terms(pa, pb);
+      int na2 = j + 4;
+      asm volatile("" : "+s"(na2));
+      pa = mine[na2];
+      pb = mine[na2 + 1];
+      __builtin_amdgcn_sched_barrier(0);
+      terms(pc, pd);
+    }
+    if (j < slen) {
+      const bool two = j + 2 < slen;
+      if (two) {
+        pc = mine[j + 2];
+        pd = mine[j + 3];
+      }
+      if (j + 1 >= slen) pb.w = 0.0f;
+      terms(pa, pb);
+      if (two) {
+        if (j + 3 >= slen) pd.w = 0.0f;
+        terms(pc, pd);
+      }
     }
 #pragma unroll
     for (int k = 0; k < TPL; ++k) {  // acc *= e^{-i 2pi C}
@@ -347,18 +423,33 @@ k_iter(const TrapCoef* __restrict__ coef, const HoloDesc* __restrict__ hd, const
   const float V2 = Vr * Vr;
   float4* rec = reinterpret_cast<float4*>(ubuf);
 
+  // the loads of the thread's own trap (coefficients, state, V) are all issued here, so the
+  // update waits for one memory round trip, not one per dependent step
+  TrapCoef c_first = {0.0f, 0.0f, 0.0f, 0.0f};
+  TrapState s_first = {0.0f, 0.0f, 0.0f, 0.0f};
+  float2 v_first = make_float2(0.0f, 0.0f);
+  if ((int)threadIdx.x < M) {
+    c_first = cf[threadIdx.x];
+    s_first = st_in[off + threadIdx.x];
+    if (upd != 0) v_first = make_float2(Vprev[2 * (off + threadIdx.x)], Vprev[2 * (off + threadIdx.x) + 1]);
+  }
+  const int G = hd[b].g, A = hd[b].a;
+  const LaneCoef<TPL> lane_first = load_lane_coef<TPL>(cf, M, G, 0, Vr, V2);
+  auto coef_of = [&](int m) { return m == (int)threadIdx.x ? c_first : cf[m]; };
   if (upd == 0) {
     for (int m = threadIdx.x; m < M; m += NT) {
-      const TrapState s = st_in[off + m];
-      stage_record<NT>(rec, cf[m], Vr, V2, s.theta_rev, s.w, m);
+      const TrapState s = m == (int)threadIdx.x ? s_first : st_in[off + m];
+      stage_record<NT>(rec, coef_of(m), Vr, V2, s.theta_rev, s.w, m);
     }
   } else {
     const bool lead = sg == 0 && r == 0;
-    update_traps<NT>(Vprev, st_in, off, M, upd, sh, lead ? stats + 3 * ((size_t)b * stat_stride + kstat) : nullptr,
-                     lead ? flag : nullptr, [&](int m, const TrapState& s) {
-                       if (lead) st_out[off + m] = s;
-                       stage_record<NT>(rec, cf[m], Vr, V2, s.theta_rev, s.w, m);
-                     });
+    auto emit = [&](int m, const TrapState& s) {
+      if (lead) st_out[off + m] = s;
+      stage_record<NT>(rec, coef_of(m), Vr, V2, s.theta_rev, s.w, m);
+    };
+    update_traps<NT, decltype(emit), true>(Vprev, st_in, off, M, upd, sh,
+                                           lead ? stats + 3 * ((size_t)b * stat_stride + kstat) : nullptr,
+                                           lead ? flag : nullptr, emit, v_first, s_first);
   }
   pad_records<NT>(rec, M);
   __syncthreads();
@@ -389,8 +480,8 @@ k_iter(const TrapCoef* __restrict__ coef, const HoloDesc* __restrict__ hd, const
   for (int i = NT * Q + threadIdx.x; i < PXN; i += NT) px[i] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
   __syncthreads();
   const int nblk = ny * nseg;
-  trap_pass_block<W, TPL, FRACT>(cf, M, hd[b].g, hd[b].a, Vr, V2, px, len, ubuf,
-                                 partial + (size_t)off * nblk + r * nseg + sg, nblk);
+  trap_pass_block<W, TPL, FRACT>(cf, M, G, A, Vr, V2, px, len, ubuf, partial + (size_t)off * nblk + r * nseg + sg,
+                                 nblk, lane_first);
 }
 
 // ------------------------------------------------------------------ stand-alone passes
@@ -465,6 +556,8 @@ k_forward(const TrapCoef* __restrict__ coef, const HoloDesc* __restrict__ hd, co
   const int S = W * A;
   const int padded = S * ((len + S - 1) / S) + 4;  // zeros past the last slice for the read-ahead
   const float* __restrict__ ph = phase + (size_t)b * nx * ny + (size_t)r * nx + cbeg;
+  const float Vr = (float)(2 * r - (ny - 1));
+  const LaneCoef<TPL> lane_first = load_lane_coef<TPL>(coef + off, M, G, 0, Vr, Vr * Vr);
   for (int i = threadIdx.x; i < padded; i += kBlock) {
     if (i < len) {
       const float U = (float)(2 * (cbeg + i) - (nx - 1));
@@ -474,10 +567,9 @@ k_forward(const TrapCoef* __restrict__ coef, const HoloDesc* __restrict__ hd, co
     }
   }
   __syncthreads();
-  const float Vr = (float)(2 * r - (ny - 1));
   const int nblk = ny * nseg;
   trap_pass_block<W, TPL, FRACT>(coef + off, M, G, A, Vr, Vr * Vr, px, len, red,
-                                 partial + (size_t)off * nblk + r * nseg + sg, nblk);
+                                 partial + (size_t)off * nblk + r * nseg + sg, nblk, lane_first);
 }
 
 // ------------------------------------------------------------------ reduce, update, finalize
