@@ -16,8 +16,11 @@ SOURCES = [os.path.join(CSRC, "hot_kernels.hip"), os.path.join(CSRC, "hot_api.cp
 OUT = os.path.join(HERE, "libhot.so")
 # packed FP32 (v_pk_*_f32) code generation stays off; the host pass warns that it does
 # not know the feature, which is harmless
+# kernel arguments: the first 16 SGPRs' worth are preloaded at wave launch (no scalar load
+# to wait for before the first memory reads of a kernel)
 FLAGS = ["-O3", "--offload-arch=gfx950", "-std=c++17", "-fPIC", "-shared",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+         "-mllvm", "-amdgpu-kernarg-preload-count=16",
          "-I" + os.path.join(ROOT, "include"), "-I" + CSRC]
 
 

@@ -437,7 +437,7 @@ IterArgs iter_args(hot_ctx* c, const Plan& P, float* phase, int K) {
   a.nt = P.nt;
   a.q = P.q;
   a.tpl = P.tpl;
-  a.m_one = P.B == 1 ? P.mmax : 0;
+  if (P.B == 1) a.one = c->h_hd[0];
   a.fract = P.fract;
   a.coef = (const TrapCoef*)c->coef.p;
   a.hd = (const HoloDesc*)c->hd.p;

@@ -60,13 +60,13 @@ struct IterArgs {
   FwdGeom fg;
   int B = 1;
   int nt = 256, q = 1, tpl = 1;  // block threads (256/512), pixels per lane (1/2), traps per lane
-  int m_one = 0;                 // B == 1: the trap count (the kernel then skips the descriptor for M)
+  HoloDesc one{};                // B == 1: the hologram's descriptor (one.m > 0), passed by value
   bool fract = false;
   const TrapCoef* coef = nullptr;
   const HoloDesc* hd = nullptr;
   const TrapState* st_in = nullptr;
   TrapState* st_out = nullptr;
-  const float* Vprev = nullptr;  // interleaved V of the previous mask (upd != 0)
+  const float* Vprev = nullptr;  // interleaved V of the previous mask (used if upd != 0; never null)
   float* stats = nullptr;
   int kstat = 0, stat_stride = 1;
   int upd = 0;                   // 0 none, 1 GS, 2 GSW

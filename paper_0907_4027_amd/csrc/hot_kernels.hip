@@ -126,6 +126,17 @@ __device__ __forceinline__ void block_reduce(float* sh, float& a, float& b, floa
   }
 }
 
+// Block-wide sum of a (every thread gets it), combined in wave order as in block_reduce.
+template <int NT>
+__device__ __forceinline__ void block_sum(float* sh, float& a) {
+  constexpr int W = NT / 64;
+  a = wave_sum(a);
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = a;
+  __syncthreads();
+  a = sh[0];
+  for (int w = 1; w < W; ++w) a += sh[w];
+}
+
 // Section 3 figures of merit and the GS/GSW update for one hologram, computed by one
 // block from V (interleaved re/im of M traps at offset off) and the current state.
 //   stats_row (3 floats) if non-null: e = sum I, u = 1 - (max-min)/(max+min), sigma = std(I)/mean(I)
@@ -151,7 +162,11 @@ __device__ void update_traps(const float* __restrict__ V, const TrapState* __res
     mx = fmaxf(mx, I);
     mn = fminf(mn, I);
   }
-  block_reduce<NT>(sh, sa, si, mx, mn);
+  if (stats_row) {
+    block_reduce<NT>(sh, sa, si, mx, mn);
+  } else {
+    block_sum<NT>(sh, sa);  // the update needs only <|V|>
+  }
   const float mean_abs = sa / (float)M;
   if (stats_row) {
     const float mu = si / (float)M;
@@ -182,7 +197,8 @@ __device__ void update_traps(const float* __restrict__ V, const TrapState* __res
       const bool tiny = amp < floor_abs;
       if (mode == 2) s.w *= mean_abs / (tiny ? floor_abs : amp);
       if (!tiny) {
-        s.theta_rad = atan2f(vi, vr);
+        const float th = phase_of(vi, vr);  // arg V in [0, 2pi], kept in (-pi, pi]
+        s.theta_rad = th > 3.14159265358979324f ? th - kTwoPi : th;
         s.theta_rev = s.theta_rad * kInv2Pi;
       }
     }
@@ -278,6 +294,9 @@ template <int TPL>
 struct LaneCoef {
   float na[TPL], ng[TPL], cc[TPL];
 };
+// Slots past M take trap M - 1's coefficients (always a valid read, and the arguments stay in
+// the sin/cos domain); their sums are never written out.  The loads are unconditional so that
+// the compiler need not wait for them where a conditional default would be merged in.
 template <int TPL>
 __device__ __forceinline__ LaneCoef<TPL> load_lane_coef(const TrapCoef* __restrict__ cf, int M, int G, int k0,
                                                         float Vr, float V2) {
@@ -286,9 +305,7 @@ __device__ __forceinline__ LaneCoef<TPL> load_lane_coef(const TrapCoef* __restri
   LaneCoef<TPL> lc;
 #pragma unroll
   for (int k = 0; k < TPL; ++k) {
-    const int m = k0 + tl + k * G;
-    TrapCoef c = {0.0f, 0.0f, 0.0f, 0.0f};
-    if (m < M) c = cf[m];
+    const TrapCoef c = cf[min(k0 + tl + k * G, M - 1)];
     lc.na[k] = -c.a;
     lc.ng[k] = -c.g;
     lc.cc[k] = __builtin_fmaf(c.g, V2, c.b * Vr);
@@ -399,15 +416,17 @@ __device__ __forceinline__ void trap_pass_block(const TrapCoef* __restrict__ cf,
 //   upd = 0: use st_in as is;  1/2: GS/GSW update from Vprev and st_in, recomputed by every
 //   block; block (0, 0, b) also writes the new state to st_out and the figures of merit of
 //   Vprev to stats[b][kstat].
-//   m_one > 0: a single hologram of m_one traps (offset 0), so the update's loads need not
-//   wait for the descriptor.
+//   one.m > 0: a single hologram whose descriptor comes by value, so no load waits for it.
+//   The arguments the first loads need lead the list (they fit the SGPRs that the kernel
+//   arguments are preloaded into at wave launch).
+//   Vprev is read even when upd == 0 (it must be a valid buffer of the launch's traps).
 // Writes phase (radians) and the trap-pass partials of the new mask.
 template <int NT, int Q, int TPL, bool FRACT>
 __global__ void __launch_bounds__(NT)
-k_iter(const TrapCoef* __restrict__ coef, const HoloDesc* __restrict__ hd, const TrapState* __restrict__ st_in,
-       TrapState* __restrict__ st_out, const float* __restrict__ Vprev, float* __restrict__ stats, int kstat,
-       int stat_stride, int upd, int* __restrict__ flag, int nx, int ny, int seg_w, int nseg, int m_one,
-       float* __restrict__ phase, float2* __restrict__ partial) {
+k_iter(HoloDesc one, const TrapCoef* __restrict__ coef, const TrapState* __restrict__ st_in,
+       const float* __restrict__ Vprev, const HoloDesc* __restrict__ hd, TrapState* __restrict__ st_out,
+       float* __restrict__ stats, int kstat, int stat_stride, int upd, int* __restrict__ flag, int nx, int ny,
+       int seg_w, int nseg, float* __restrict__ phase, float2* __restrict__ partial) {
   constexpr int W = NT / 64;
   constexpr int PXN = NT * Q + 136;  // slices cover < len + S <= len + 128 entries, plus 3 read ahead
   constexpr int REDN = W * 64 * TPL;                   // float2 slice partials
@@ -417,23 +436,19 @@ k_iter(const TrapCoef* __restrict__ coef, const HoloDesc* __restrict__ hd, const
   __shared__ float2 ubuf[UN];  // pixel-pass records, then slice partials in the trap pass
   __shared__ float sh[8 * W];
   const int b = blockIdx.z, r = blockIdx.y, sg = blockIdx.x;
-  const int M = m_one > 0 ? m_one : hd[b].m, off = m_one > 0 ? 0 : hd[b].off;
+  const HoloDesc d = one.m > 0 ? one : hd[b];
+  const int M = d.m, off = d.off, G = d.g, A = d.a;
   const TrapCoef* __restrict__ cf = coef + off;
   const float Vr = (float)(2 * r - (ny - 1));
   const float V2 = Vr * Vr;
   float4* rec = reinterpret_cast<float4*>(ubuf);
 
-  // the loads of the thread's own trap (coefficients, state, V) are all issued here, so the
-  // update waits for one memory round trip, not one per dependent step
-  TrapCoef c_first = {0.0f, 0.0f, 0.0f, 0.0f};
-  TrapState s_first = {0.0f, 0.0f, 0.0f, 0.0f};
-  float2 v_first = make_float2(0.0f, 0.0f);
-  if ((int)threadIdx.x < M) {
-    c_first = cf[threadIdx.x];
-    s_first = st_in[off + threadIdx.x];
-    if (upd != 0) v_first = make_float2(Vprev[2 * (off + threadIdx.x)], Vprev[2 * (off + threadIdx.x) + 1]);
-  }
-  const int G = hd[b].g, A = hd[b].a;
+  // Every read of the block's own trap data is issued here, unconditionally (threads past M read
+  // trap M - 1 and ignore it), so the update waits for one memory round trip.
+  const int tm = min((int)threadIdx.x, M - 1);
+  const TrapCoef c_first = cf[tm];
+  const TrapState s_first = st_in[off + tm];
+  const float2 v_first = make_float2(Vprev[2 * (off + tm)], Vprev[2 * (off + tm) + 1]);
   const LaneCoef<TPL> lane_first = load_lane_coef<TPL>(cf, M, G, 0, Vr, V2);
   auto coef_of = [&](int m) { return m == (int)threadIdx.x ? c_first : cf[m]; };
   if (upd == 0) {
@@ -1107,11 +1122,11 @@ __global__ void k_import_w(const float* __restrict__ w0, TrapState* __restrict__
 
 template <int NT, int Q, int TPL, bool FRACT>
 hipError_t iter_t(hipStream_t s, const IterArgs& a) {
-  if (a.fg.seg_w > NT * Q) return hipErrorInvalidValue;
+  if (a.fg.seg_w > NT * Q || a.Vprev == nullptr) return hipErrorInvalidValue;
   dim3 grid(a.fg.nseg, a.fg.ny, a.B);
-  hipLaunchKernelGGL((k_iter<NT, Q, TPL, FRACT>), grid, dim3(NT), 0, s, a.coef, a.hd, a.st_in, a.st_out, a.Vprev,
-                     a.stats, a.kstat, a.stat_stride, a.upd, a.flag, a.fg.nx, a.fg.ny, a.fg.seg_w, a.fg.nseg,
-                     a.B == 1 ? a.m_one : 0, a.phase, a.partial);
+  hipLaunchKernelGGL((k_iter<NT, Q, TPL, FRACT>), grid, dim3(NT), 0, s, a.B == 1 ? a.one : HoloDesc{}, a.coef,
+                     a.st_in, a.Vprev, a.hd, a.st_out, a.stats, a.kstat, a.stat_stride, a.upd, a.flag, a.fg.nx,
+                     a.fg.ny, a.fg.seg_w, a.fg.nseg, a.phase, a.partial);
   return hipGetLastError();
 }
 
