@@ -189,9 +189,12 @@ int hot_encode_u8(hot_ctx* ctx, int64_t n, const float* phase, uint8_t* frame);
  * launches four groups of kernels `reps` times each, back to back on the context's stream
  * (current variant and tuning), each group bracketed by HIP events, and writes the mean
  * device time per launch in milliseconds to
- *   ms[0]  one GSW iteration's main work (on-the-fly and separable: the fused update + pixel
- *          pass + trap pass kernel; stored: the pixel and trap pass kernels)
- *   ms[1]  the reduction of the trap-pass partials into V
+ *   ms[0]  one GSW iteration's main work (on-the-fly: the fused update + pixel pass + trap pass
+ *          kernel, which also sums the trap pass into V's fixed-point accumulators; separable:
+ *          the fused update + both passes on the matrix cores; stored: the pixel and trap
+ *          pass kernels)
+ *   ms[1]  the reduction into V (stored and separable: of the per-block partials, once per
+ *          iteration; on-the-fly: of the fixed-point accumulators, once per solve)
  *   ms[2]  the pixel pass alone   ms[3]  the trap pass alone
  * phase (device, N floats) and V (device, 2M floats) are scratch outputs.  Synchronises
  * the stream. */

@@ -73,6 +73,7 @@ struct hot_ctx {
   std::vector<GraphEntry> graphs;
   uint64_t graph_clock = 0;
   DevBuf coef, st, hd, partial, stats, flag, amat, efield;
+  DevBuf acc;  // direct path: 3 rotating buffers of fixed-point trap sums [kAccRegions][T][2] u64
   Staging ring[kRing];
   int ring_pos = 0;
   int* flag_host = nullptr;  // pinned
@@ -226,6 +227,9 @@ struct Plan {
   int nblk_stored = 0;
   // separable variant: blocks of 16 rows x 16 sep_w columns, sep_sc traps per LDS super-chunk
   int sep_w = 4, nblk_sep = 0, sep_sc = 16;
+  // direct path fixed point: scale 2^s with s = 61 - ceil(log2 N); every block sum and every
+  // trap's total has magnitude <= N, so no sum leaves +-2^61
+  float acc_scale = 0.0f, acc_unscale = 0.0f;
 };
 
 FwdGeom row_segments(int nx, int ny, int segmax) {
@@ -244,6 +248,12 @@ int prepare(hot_ctx* c, const hot_slm* slm, int B, const int32_t* counts, const 
   P.nx = slm->nx;
   P.ny = slm->ny;
   P.n = slm->nx * slm->ny;
+  {
+    int lg = 0;
+    while ((1LL << lg) < (long long)P.n) ++lg;
+    P.acc_scale = (float)std::ldexp(1.0, 61 - lg);
+    P.acc_unscale = (float)(std::ldexp(1.0, lg - 61) / (double)P.n);
+  }
   P.T = 0;
   P.mmax = 0;
   for (int b = 0; b < B; ++b) {
@@ -430,8 +440,17 @@ SepArgs sep_args(hot_ctx* c, const Plan& P, int mode, float* phase, int K) {
   return a;
 }
 
+// Buffer i (0..2) of the direct path's rotating fixed-point sums.
+unsigned long long* acc_buf(hot_ctx* c, const Plan& P, int i) {
+  return (unsigned long long*)c->acc.p + (size_t)i * 2 * kAccRegions * P.T;
+}
+int ensure_acc(hot_ctx* c, const Plan& P) { return ensure(c, c->acc, 3 * sizeof(uint64_t) * 2 * kAccRegions * P.T); }
+
 IterArgs iter_args(hot_ctx* c, const Plan& P, float* phase, int K) {
   IterArgs a;
+  a.T = P.T;
+  a.acc_scale = P.acc_scale;
+  a.acc_unscale = P.acc_unscale;
   a.fg = P.fg;
   a.B = P.B;
   a.nt = P.nt;
@@ -445,7 +464,6 @@ IterArgs iter_args(hot_ctx* c, const Plan& P, float* phase, int K) {
   a.stat_stride = K + 1;
   a.flag = (int*)c->flag.p;
   a.phase = phase;
-  a.partial = (float2*)c->partial.p;
   return a;
 }
 
@@ -461,9 +479,10 @@ int solve(hot_ctx* c, const hot_slm* slm, int B, const int32_t* counts, const do
   const bool separable = variant == HOT_SEPARABLE;
   const int nblk = stored ? P.nblk_stored : separable ? P.nblk_sep : P.fg.nblk();
   if ((rc = upload_tables(c, slm, P, xyz, counts))) return rc;
-  if ((rc = ensure(c, c->partial, sizeof(float2) * (size_t)P.T * nblk))) return rc;
+  if ((stored || separable) && (rc = ensure(c, c->partial, sizeof(float2) * (size_t)P.T * nblk))) return rc;
   if ((rc = ensure(c, c->stats, sizeof(float) * 3 * (size_t)B * (K + 1)))) return rc;
   if (stored && (rc = ensure_stored(c, P))) return rc;
+  if (!stored && !separable && (rc = ensure_acc(c, P))) return rc;
   TrapState* st[2] = {(TrapState*)c->st.p, (TrapState*)c->st.p + P.T};
   if (w0) HIP_TRY(launch_import_w(c->stream, w0, st[0], P.T));
 
@@ -489,16 +508,21 @@ int solve(hot_ctx* c, const hot_slm* slm, int B, const int32_t* counts, const do
         if (e == hipSuccess) e = launch_reduce(s, B, P.mmax, nblk, inv_n, part, hd, V);
       }
     } else if (!stored) {
+      // one launch per iteration: launch k reads buffer k % 3, adds into (k + 1) % 3 (buffer 1 is
+      // cleared first, the others by the launches) and clears (k + 2) % 3
       IterArgs a = iter_args(c, P, phase, K);
+      e = launch_fill_u32(s, (unsigned*)acc_buf(c, P, 1), 0u, 4 * kAccRegions * P.T);
       for (int k = 0; k <= K && e == hipSuccess; ++k) {
         a.upd = k == 0 ? 0 : upd;
         a.st_in = k == 0 ? st[0] : st[(k - 1) & 1];
         a.st_out = st[k & 1];
-        a.Vprev = V;
+        a.acc_in = acc_buf(c, P, k % 3);
+        a.acc_out = acc_buf(c, P, (k + 1) % 3);
+        a.acc_zero = acc_buf(c, P, (k + 2) % 3);
         a.kstat = k - 1;
         e = launch_iter(s, a);
-        if (e == hipSuccess) e = launch_reduce(s, B, P.mmax, nblk, inv_n, part, hd, V);
       }
+      if (e == hipSuccess) e = launch_collect(s, P.T, acc_buf(c, P, (K + 1) % 3), P.acc_unscale, V);
     } else {
       for (int k = 0; k <= K && e == hipSuccess; ++k) {
         if (k > 0)
@@ -526,7 +550,7 @@ int solve(hot_ctx* c, const hot_slm* slm, int B, const int32_t* counts, const do
                                  (uint64_t)(uintptr_t)c->coef.p, (uint64_t)(uintptr_t)c->st.p,
                                  (uint64_t)(uintptr_t)c->hd.p, (uint64_t)(uintptr_t)c->partial.p,
                                  (uint64_t)(uintptr_t)c->stats.p, (uint64_t)(uintptr_t)c->amat.p,
-                                 (uint64_t)(uintptr_t)c->efield.p};
+                                 (uint64_t)(uintptr_t)c->efield.p, (uint64_t)(uintptr_t)c->acc.p};
     hot_ctx::GraphEntry* hit = nullptr;
     for (auto& g : c->graphs)
       if (g.key == key) hit = &g;
@@ -838,17 +862,25 @@ int hot_time_passes(hot_ctx* c, const hot_slm* slm, int32_t M, const double* xyz
   if ((rc = ensure(c, c->partial, sizeof(float2) * (size_t)P.T * nblk))) return rc;
   if ((rc = ensure(c, c->stats, sizeof(float) * 3 * 2))) return rc;
   if (stored && (rc = ensure_stored(c, P))) return rc;
+  if (!stored && !separable && (rc = ensure_acc(c, P))) return rc;
   const TrapCoef* coef = (const TrapCoef*)c->coef.p;
   TrapState* st[2] = {(TrapState*)c->st.p, (TrapState*)c->st.p + P.T};
   const HoloDesc* hd = (const HoloDesc*)c->hd.p;
   float2* part = (float2*)c->partial.p;
   const float inv_n = (float)(1.0 / (double)P.n);
-  // group 0: one GSW iteration's main kernel (fused passes, or the stored pixel + trap pass)
+  // group 0: one GSW iteration's main kernel (fused passes, or the stored pixel + trap pass).
+  // The fused kernel reads buffer 0 (filled beforehand by a pass over the theta0 mask), adds
+  // into buffer 1 (its sums then wrap around over the repetitions: integers, and unused) and
+  // clears buffer 2.
   IterArgs a = iter_args(c, P, phase, 1);
   a.upd = 2;
   a.st_in = st[0];
   a.st_out = st[1];
-  a.Vprev = V;
+  if (!stored && !separable) {
+    a.acc_in = acc_buf(c, P, 0);
+    a.acc_out = acc_buf(c, P, 1);
+    a.acc_zero = acc_buf(c, P, 2);
+  }
   SepArgs sa = sep_args(c, P, 0, phase, 1);
   sa.upd = 2;
   sa.st_in = st[0];
@@ -868,9 +900,22 @@ int hot_time_passes(hot_ctx* c, const hot_slm* slm, int32_t M, const double* xyz
     if (e != hipSuccess) return e;
     return launch_forward_stored(c->stream, P.n, 1, (const float2*)c->amat.p, (const float2*)c->efield.p, hd, part);
   };
+  // group 1: the reduction to V (per iteration on the stored and separable paths; once per solve,
+  // from the fixed-point sums, on the direct path)
   auto g1 = [&]() {
-    return launch_reduce(c->stream, 1, P.mmax, stored ? P.nblk_stored : separable ? P.nblk_sep : P.fg.nblk(), inv_n,
-                         part, hd, V);
+    if (!stored && !separable) return launch_collect(c->stream, P.T, acc_buf(c, P, 0), P.acc_unscale, V);
+    return launch_reduce(c->stream, 1, P.mmax, stored ? P.nblk_stored : P.nblk_sep, inv_n, part, hd, V);
+  };
+  // the direct path's buffer 0: sums of the theta0 mask (a pass without update)
+  auto prime = [&]() -> hipError_t {
+    if (stored || separable) return hipSuccess;
+    IterArgs p0 = a;
+    p0.upd = 0;
+    p0.acc_in = acc_buf(c, P, 2);
+    p0.acc_out = acc_buf(c, P, 0);
+    p0.acc_zero = acc_buf(c, P, 1);
+    hipError_t e = launch_fill_u32(c->stream, (unsigned*)acc_buf(c, P, 0), 0u, 4 * kAccRegions * P.T);
+    return e == hipSuccess ? launch_iter(c->stream, p0) : e;
   };
   auto g2 = [&]() {
     if (separable) return sep_mode(2);
@@ -888,11 +933,11 @@ int hot_time_passes(hot_ctx* c, const hot_slm* slm, int32_t M, const double* xyz
   for (auto& e : ev) HIP_TRY(hipEventCreate(&e));
   int out = HOT_OK;
   do {
-    // V must hold a real trap field before the fused kernel's update reads it
+    // V (and the direct path's buffer 0) must hold a real trap field before an update reads it
     if (g2() != hipSuccess || g3() != hipSuccess ||
         launch_reduce(c->stream, 1, P.mmax, stored ? P.nblk_stored : separable ? P.nblk_sep : P.fgf.nblk(), inv_n,
                       part, stored || separable ? hd : hd + 1, V) != hipSuccess ||
-        g0() != hipSuccess || g1() != hipSuccess) {
+        prime() != hipSuccess || g0() != hipSuccess || g1() != hipSuccess) {
       out = fail(HOT_EDEVICE, "launch failed");
       break;
     }

@@ -55,7 +55,12 @@ struct FwdGeom {
   int nblk() const { return nseg * ny; }
 };
 
-// One fused iteration: (optional GS/GSW update) -> pixel pass -> trap pass partials.
+// One fused iteration: (optional GS/GSW update) -> pixel pass -> trap pass, its sums added to acc_out.
+// Direct path: each iteration launch adds its per-block trap sums, as 64-bit fixed point, into
+// kAccRegions regions (one per XCD of an MI355X; waves of XCD x use region x & 7), laid out
+// [region][trap][re, im]; three such buffers rotate over the iterations.
+constexpr int kAccRegions = 8;
+
 struct IterArgs {
   FwdGeom fg;
   int B = 1;
@@ -66,18 +71,24 @@ struct IterArgs {
   const HoloDesc* hd = nullptr;
   const TrapState* st_in = nullptr;
   TrapState* st_out = nullptr;
-  const float* Vprev = nullptr;  // interleaved V of the previous mask (used if upd != 0; never null)
+  const unsigned long long* acc_in = nullptr;  // sums of the previous mask (used if upd != 0; never null)
+  unsigned long long* acc_out = nullptr;       // sums of this launch's mask (added to; cleared beforehand)
+  unsigned long long* acc_zero = nullptr;      // cleared here for the launch after next
+  int T = 0;                                   // traps of all holograms of the launch
+  float acc_scale = 0.0f, acc_unscale = 0.0f;  // 2^s, and 2^-s / N
   float* stats = nullptr;
   int kstat = 0, stat_stride = 1;
   int upd = 0;                   // 0 none, 1 GS, 2 GSW
   int* flag = nullptr;
   float* phase = nullptr;
-  float2* partial = nullptr;
 };
 
 // ---- launchers (hot_kernels.hip); all enqueue on `s` and return hipError_t ----
 
 hipError_t launch_iter(hipStream_t s, const IterArgs& a);
+
+// V (2T floats, interleaved) from one buffer of the direct path's fixed-point sums.
+hipError_t launch_collect(hipStream_t s, int T, const unsigned long long* acc, float unscale, float* V);
 
 // Pixel pass alone (Eq. 3 with weights).  mode 0 writes the phase; mode 1 (adjoint) reads
 // `phase` and G (2T floats, interleaved) and writes grad[b][j] = (1/N) Im(e^{-i phi_j} sum_m G_m e^{i Delta_j^m}).

@@ -29,6 +29,9 @@ namespace {
 constexpr float kInv2Pi = 0.159154943091895336f;  // FP32(1 / (2 pi))
 constexpr float kTwoPi = 6.28318530717958648f;    // FP32(2 pi)
 
+// The XCD (accelerator complex die) the wave runs on: hardware register XCC_ID, bits 3:0.
+__device__ __forceinline__ int xcc_id() { return __builtin_amdgcn_s_getreg(20 | (0 << 6) | ((4 - 1) << 11)) & 15; }
+
 template <bool FRACT>
 __device__ __forceinline__ float to_period(float t) {
   if constexpr (FRACT) return __builtin_amdgcn_fractf(t);
@@ -137,20 +140,44 @@ __device__ __forceinline__ void block_sum(float* sh, float& a) {
   for (int w = 1; w < W; ++w) a += sh[w];
 }
 
+// V of trap k (local index) of a hologram: from an interleaved (re, im) array ...
+struct VArray {
+  const float* __restrict__ V;
+  int off;
+  __device__ float2 operator()(int k) const { return make_float2(V[2 * (off + k)], V[2 * (off + k) + 1]); }
+};
+// ... or from the fixed-point sums of the direct path: kAccRegions regions of T (re, im)
+// pairs of 64-bit integers (two's complement), V = (sum over regions) * unscale.
+struct VAcc {
+  const ulonglong2* __restrict__ acc;
+  int T, off;
+  float unscale;
+  __device__ float2 operator()(int k) const {
+    unsigned long long re = 0, im = 0;
+#pragma unroll
+    for (int r = 0; r < kAccRegions; ++r) {
+      const ulonglong2 v = acc[(size_t)r * T + off + k];
+      re += v.x;
+      im += v.y;
+    }
+    return make_float2((float)(long long)re * unscale, (float)(long long)im * unscale);
+  }
+};
+
 // Section 3 figures of merit and the GS/GSW update for one hologram, computed by one
-// block from V (interleaved re/im of M traps at offset off) and the current state.
+// block from V (vmem(k) for its M traps) and the current state.
 //   stats_row (3 floats) if non-null: e = sum I, u = 1 - (max-min)/(max+min), sigma = std(I)/mean(I)
 //   mode 0: no update; 1 (GS): theta_m <- arg V_m; 2 (GSW): also w_m <- w_m <|V|>/|V_m|
 // emit(m, state) is called once per trap m, by the thread that owns it.  <|V|> = 0 leaves
 // the state unchanged and raises *flag (if non-null).  With PRE, trap threadIdx.x's V and state
 // come from vpre / spre (loaded earlier by the caller) instead of memory.
-template <int NT, class Emit, bool PRE = false>
-__device__ void update_traps(const float* __restrict__ V, const TrapState* __restrict__ st_in, int off, int M,
-                             int mode, float* sh, float* stats_row, int* flag, Emit emit,
-                             float2 vpre = make_float2(0.0f, 0.0f), TrapState spre = TrapState{}) {
+template <int NT, class VGet, class Emit, bool PRE = false>
+__device__ void update_traps(VGet vmem, const TrapState* __restrict__ st_in, int off, int M, int mode, float* sh,
+                             float* stats_row, int* flag, Emit emit, float2 vpre = make_float2(0.0f, 0.0f),
+                             TrapState spre = TrapState{}) {
   auto getv = [&](int k) {
     if (PRE && k == (int)threadIdx.x) return vpre;
-    return make_float2(V[2 * (off + k)], V[2 * (off + k) + 1]);
+    return vmem(k);
   };
   float sa = 0.0f, si = 0.0f, mx = -1.0f, mn = 3.0e38f;
   for (int k = threadIdx.x; k < M; k += NT) {
@@ -287,7 +314,7 @@ __device__ __forceinline__ void pad_records(float4* rec, int M) {
 //   acc += mask (cos t, sin t)              2 VALU
 // The row-constant part of Eq. 2, C_m = g V^2 + b V, is taken out of the sum: each lane's
 // accumulator is turned by e^{-i 2pi C_m} once, after its pixels.  The S slice partials of
-// each trap are then summed in slice order through LDS `red` and written to out[m * nblk].
+// each trap are then summed in slice order through LDS `red` and handed to store(m, sum).
 // The coefficients one trap-pass lane needs for the traps it owns in one chunk: -a, -g and the
 // row constant C_m = g V^2 + b V (revolutions).  Traps past M get zeros (their sums are unused).
 template <int TPL>
@@ -315,10 +342,10 @@ __device__ __forceinline__ LaneCoef<TPL> load_lane_coef(const TrapCoef* __restri
 
 // `first` holds the lane's coefficients of the first chunk (k0 = 0), loaded by the caller before
 // its own global stores, so that waiting for them does not wait for those stores too.
-template <int W, int TPL, bool FRACT>
+template <int W, int TPL, bool FRACT, class Store>
 __device__ __forceinline__ void trap_pass_block(const TrapCoef* __restrict__ cf, int M, int G, int A, float Vr,
-                                                float V2, const float4* px, int len, float2* red,
-                                                float2* __restrict__ out, int nblk, const LaneCoef<TPL>& first) {
+                                                float V2, const float4* px, int len, float2* red, Store store,
+                                                const LaneCoef<TPL>& first) {
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int s = lane / G, tl = lane - s * G;
   const bool active = s < A;
@@ -404,7 +431,7 @@ __device__ __forceinline__ void trap_pass_block(const TrapCoef* __restrict__ cf,
           acc.x += v.x;
           acc.y += v.y;
         }
-        out[(size_t)m * nblk] = acc;
+        store(m, acc);
       }
     }
   }
@@ -413,20 +440,26 @@ __device__ __forceinline__ void trap_pass_block(const TrapCoef* __restrict__ cf,
 // ------------------------------------------------------------------ fused iteration kernel
 //
 // Grid (nseg, ny, B), NT threads, one row segment (seg_w <= NT * Q pixels) per block.
-//   upd = 0: use st_in as is;  1/2: GS/GSW update from Vprev and st_in, recomputed by every
-//   block; block (0, 0, b) also writes the new state to st_out and the figures of merit of
-//   Vprev to stats[b][kstat].
+//   upd = 0: use st_in as is;  1/2: GS/GSW update from V of the previous mask and st_in,
+//   recomputed by every block; block (0, 0, b) also writes the new state to st_out and the
+//   figures of merit of that V to stats[b][kstat].
+//   V is not a separate array: the previous launch added each block's trap sums to acc_in as
+//   64-bit fixed point (value * scale, truncated), one region per XCD (the XCC_ID of the adding
+//   wave) so that the atomics of different XCDs do not contend; integer sums do not depend on
+//   the order of the adds, so the result is deterministic.  This launch adds its own sums to
+//   acc_out, and block (0, 0, b) clears hologram b's part of acc_zero for the launch after next.
+//   acc_in is read even when upd == 0 (it must be a valid buffer; the values are then unused).
 //   one.m > 0: a single hologram whose descriptor comes by value, so no load waits for it.
 //   The arguments the first loads need lead the list (they fit the SGPRs that the kernel
 //   arguments are preloaded into at wave launch).
-//   Vprev is read even when upd == 0 (it must be a valid buffer of the launch's traps).
-// Writes phase (radians) and the trap-pass partials of the new mask.
+// Writes phase (radians).
 template <int NT, int Q, int TPL, bool FRACT>
 __global__ void __launch_bounds__(NT)
 k_iter(HoloDesc one, const TrapCoef* __restrict__ coef, const TrapState* __restrict__ st_in,
-       const float* __restrict__ Vprev, const HoloDesc* __restrict__ hd, TrapState* __restrict__ st_out,
+       const ulonglong2* __restrict__ acc_in, const HoloDesc* __restrict__ hd, TrapState* __restrict__ st_out,
+       ulonglong2* __restrict__ acc_out, ulonglong2* __restrict__ acc_zero, int T, float scale, float unscale,
        float* __restrict__ stats, int kstat, int stat_stride, int upd, int* __restrict__ flag, int nx, int ny,
-       int seg_w, int nseg, float* __restrict__ phase, float2* __restrict__ partial) {
+       int seg_w, float* __restrict__ phase) {
   constexpr int W = NT / 64;
   constexpr int PXN = NT * Q + 136;  // slices cover < len + S <= len + 128 entries, plus 3 read ahead
   constexpr int REDN = W * 64 * TPL;                   // float2 slice partials
@@ -442,14 +475,22 @@ k_iter(HoloDesc one, const TrapCoef* __restrict__ coef, const TrapState* __restr
   const float Vr = (float)(2 * r - (ny - 1));
   const float V2 = Vr * Vr;
   float4* rec = reinterpret_cast<float4*>(ubuf);
+  const bool lead = sg == 0 && r == 0;
+  const VAcc vacc{acc_in, T, off, unscale};
 
   // Every read of the block's own trap data is issued here, unconditionally (threads past M read
   // trap M - 1 and ignore it), so the update waits for one memory round trip.
   const int tm = min((int)threadIdx.x, M - 1);
   const TrapCoef c_first = cf[tm];
   const TrapState s_first = st_in[off + tm];
-  const float2 v_first = make_float2(Vprev[2 * (off + tm)], Vprev[2 * (off + tm) + 1]);
+  const float2 v_first = vacc(tm);
   const LaneCoef<TPL> lane_first = load_lane_coef<TPL>(cf, M, G, 0, Vr, V2);
+  if (lead) {
+    for (int i = threadIdx.x; i < kAccRegions * M; i += NT) {
+      const int g = i / M;
+      acc_zero[(size_t)g * T + off + (i - g * M)] = make_ulonglong2(0ull, 0ull);
+    }
+  }
   auto coef_of = [&](int m) { return m == (int)threadIdx.x ? c_first : cf[m]; };
   if (upd == 0) {
     for (int m = threadIdx.x; m < M; m += NT) {
@@ -457,14 +498,13 @@ k_iter(HoloDesc one, const TrapCoef* __restrict__ coef, const TrapState* __restr
       stage_record<NT>(rec, coef_of(m), Vr, V2, s.theta_rev, s.w, m);
     }
   } else {
-    const bool lead = sg == 0 && r == 0;
     auto emit = [&](int m, const TrapState& s) {
       if (lead) st_out[off + m] = s;
       stage_record<NT>(rec, coef_of(m), Vr, V2, s.theta_rev, s.w, m);
     };
-    update_traps<NT, decltype(emit), true>(Vprev, st_in, off, M, upd, sh,
-                                           lead ? stats + 3 * ((size_t)b * stat_stride + kstat) : nullptr,
-                                           lead ? flag : nullptr, emit, v_first, s_first);
+    update_traps<NT, VAcc, decltype(emit), true>(vacc, st_in, off, M, upd, sh,
+                                                 lead ? stats + 3 * ((size_t)b * stat_stride + kstat) : nullptr,
+                                                 lead ? flag : nullptr, emit, v_first, s_first);
   }
   pad_records<NT>(rec, M);
   __syncthreads();
@@ -494,9 +534,15 @@ k_iter(HoloDesc one, const TrapCoef* __restrict__ coef, const TrapState* __restr
   }
   for (int i = NT * Q + threadIdx.x; i < PXN; i += NT) px[i] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
   __syncthreads();
-  const int nblk = ny * nseg;
-  trap_pass_block<W, TPL, FRACT>(cf, M, G, A, Vr, V2, px, len, ubuf, partial + (size_t)off * nblk + r * nseg + sg,
-                                 nblk, lane_first);
+  ulonglong2* __restrict__ mine = acc_out + (size_t)(xcc_id() & (kAccRegions - 1)) * T + off;
+  auto add_sum = [&](int m, float2 v) {
+    unsigned long long* p = reinterpret_cast<unsigned long long*>(mine + m);
+    __hip_atomic_fetch_add(p, (unsigned long long)(long long)(v.x * scale), __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_fetch_add(p + 1, (unsigned long long)(long long)(v.y * scale), __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
+  };
+  trap_pass_block<W, TPL, FRACT>(cf, M, G, A, Vr, V2, px, len, ubuf, add_sum, lane_first);
 }
 
 // ------------------------------------------------------------------ stand-alone passes
@@ -583,8 +629,9 @@ k_forward(const TrapCoef* __restrict__ coef, const HoloDesc* __restrict__ hd, co
   }
   __syncthreads();
   const int nblk = ny * nseg;
+  float2* __restrict__ out = partial + (size_t)off * nblk + r * nseg + sg;
   trap_pass_block<W, TPL, FRACT>(coef + off, M, G, A, Vr, Vr * Vr, px, len, red,
-                                 partial + (size_t)off * nblk + r * nseg + sg, nblk, lane_first);
+                                 [&](int m, float2 v) { out[(size_t)m * nblk] = v; }, lane_first);
 }
 
 // ------------------------------------------------------------------ reduce, update, finalize
@@ -613,6 +660,16 @@ k_reduce(const float2* __restrict__ partial, const HoloDesc* __restrict__ hd, in
   }
 }
 
+// V of all T traps from the fixed-point region sums of the direct path (one thread per trap).
+__global__ void __launch_bounds__(256)
+k_collect(const ulonglong2* __restrict__ acc, int T, float unscale, float* __restrict__ V) {
+  const int t = blockIdx.x * 256 + threadIdx.x;
+  if (t >= T) return;
+  const float2 v = VAcc{acc, T, 0, unscale}(t);
+  V[2 * t] = v.x;
+  V[2 * t + 1] = v.y;
+}
+
 // One block per hologram: figures of merit of V into stats[b][kstat] and, for mode 1/2,
 // the GS/GSW update st_in -> st_out (st_out may equal st_in).
 __global__ void __launch_bounds__(256)
@@ -621,7 +678,7 @@ k_update(const float* __restrict__ V, const HoloDesc* __restrict__ hd, const Tra
   __shared__ float sh[8 * 4];
   const int b = blockIdx.x;
   const int M = hd[b].m, off = hd[b].off;
-  update_traps<256>(V, st_in, off, M, mode, sh, stats + 3 * ((size_t)b * stat_stride + kstat), flag,
+  update_traps<256>(VArray{V, off}, st_in, off, M, mode, sh, stats + 3 * ((size_t)b * stat_stride + kstat), flag,
                     [&](int m, const TrapState& s) {
                       if (mode != 0) st_out[off + m] = s;
                     });
@@ -964,9 +1021,9 @@ k_sep(const TrapCoef* __restrict__ coef, const HoloDesc* __restrict__ hd, const 
         if (lead) st_out[off + m] = st;
         cw[m] = trap_weight(st);
       };
-      update_traps<NT, decltype(emit), true>(vin, st_in, off, M, upd, sh,
-                                             lead ? stats + 3 * ((size_t)b * stat_stride + kstat) : nullptr,
-                                             lead ? flag : nullptr, emit, v_first, s_first);
+      update_traps<NT, VArray, decltype(emit), true>(VArray{vin, off}, st_in, off, M, upd, sh,
+                                                     lead ? stats + 3 * ((size_t)b * stat_stride + kstat) : nullptr,
+                                                     lead ? flag : nullptr, emit, v_first, s_first);
     }
     for (int m = M + (int)threadIdx.x; m < Mp; m += NT) cw[m] = make_float2(0.0f, 0.0f);
     __syncthreads();
@@ -1122,11 +1179,12 @@ __global__ void k_import_w(const float* __restrict__ w0, TrapState* __restrict__
 
 template <int NT, int Q, int TPL, bool FRACT>
 hipError_t iter_t(hipStream_t s, const IterArgs& a) {
-  if (a.fg.seg_w > NT * Q || a.Vprev == nullptr) return hipErrorInvalidValue;
+  if (a.fg.seg_w > NT * Q || !a.acc_in || !a.acc_out || !a.acc_zero || a.T < 1) return hipErrorInvalidValue;
   dim3 grid(a.fg.nseg, a.fg.ny, a.B);
   hipLaunchKernelGGL((k_iter<NT, Q, TPL, FRACT>), grid, dim3(NT), 0, s, a.B == 1 ? a.one : HoloDesc{}, a.coef,
-                     a.st_in, a.Vprev, a.hd, a.st_out, a.stats, a.kstat, a.stat_stride, a.upd, a.flag, a.fg.nx,
-                     a.fg.ny, a.fg.seg_w, a.fg.nseg, a.phase, a.partial);
+                     a.st_in, (const ulonglong2*)a.acc_in, a.hd, a.st_out, (ulonglong2*)a.acc_out,
+                     (ulonglong2*)a.acc_zero, a.T, a.acc_scale, a.acc_unscale, a.stats, a.kstat, a.stat_stride,
+                     a.upd, a.flag, a.fg.nx, a.fg.ny, a.fg.seg_w, a.phase);
   return hipGetLastError();
 }
 
@@ -1221,6 +1279,11 @@ hipError_t launch_reduce(hipStream_t s, int B, int mmax, int nblk, float inv_n, 
                          const HoloDesc* hd, float* V) {
   dim3 grid((mmax + 3) / 4, B);
   hipLaunchKernelGGL(k_reduce, grid, dim3(256), 0, s, partial, hd, nblk, inv_n, V);
+  return hipGetLastError();
+}
+
+hipError_t launch_collect(hipStream_t s, int T, const unsigned long long* acc, float unscale, float* V) {
+  hipLaunchKernelGGL(k_collect, dim3((T + 255) / 256), dim3(256), 0, s, (const ulonglong2*)acc, T, unscale, V);
   return hipGetLastError();
 }
 

@@ -203,7 +203,8 @@ class Context:
         return frame
 
     def hot_time_passes(self, slm, xyz, theta0, reps: int = 20) -> np.ndarray:
-        """Mean device ms per launch of [iteration kernel, reduce, pixel pass alone, trap pass alone]."""
+        """Mean device ms per launch, back to back, of [iteration kernel, reduction into V, pixel pass
+        alone, trap pass alone] (the reduction runs once per solve on the on-the-fly path)."""
         s = as_slm(slm)
         x = _host_f64(xyz, cols=3)
         M = x.shape[0]
