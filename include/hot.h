@@ -108,8 +108,11 @@ enum hot_tuning_key {
                                    sequence when shapes and buffers repeat; 0: launch eagerly */
   HOT_TUNE_SEP_WAVES = 6,       /* separable variant: waves per block (1, 2 or 4), each wave a tile
                                    of 16 x 16 pixels */
-  HOT_TUNE_SEP_CHUNK = 7        /* separable variant: traps whose tables a block holds in LDS at
+  HOT_TUNE_SEP_CHUNK = 7,       /* separable variant: traps whose tables a block holds in LDS at
                                    once, a multiple of 16 (more are streamed in chunks of this size) */
+  HOT_TUNE_ROWS = 8             /* on-the-fly iteration kernel: rows per block, 1 or 2 (two rows share
+                                   one GS/GSW update and one set of trap-sum additions; 256-thread
+                                   rows only) */
 };
 int hot_set_tuning(hot_ctx* ctx, int key, int value);
 

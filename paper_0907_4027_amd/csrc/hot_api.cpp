@@ -62,7 +62,7 @@ struct hot_ctx {
   hipStream_t stream = nullptr;
   hipStream_t own_stream = nullptr;
   int variant = HOT_ONTHEFLY;
-  int tune_q = 0, tune_tpl = 0, tune_seg = 0, tune_amax = 0, tune_sepw = 0, tune_sepc = 0;
+  int tune_q = 0, tune_tpl = 0, tune_seg = 0, tune_amax = 0, tune_sepw = 0, tune_sepc = 0, tune_rows = 0;
   int use_graphs = 1;
   // captured launch sequences of solve(), keyed by everything they bake in (shapes, pointers)
   struct GraphEntry {
@@ -220,7 +220,7 @@ struct Plan {
   bool fract = false;
   // fused iteration kernel: row segments of <= nt*q pixels, nt threads, q pixels per lane
   FwdGeom fg{};
-  int nt = 256, q = 1, tpl = 1;
+  int nt = 256, q = 1, tpl = 1, rows = 1;
   // stand-alone trap pass (hot_forward_V): row segments of <= kSegMax pixels, kBlock threads
   FwdGeom fgf{};
   int tplf = 1;
@@ -270,6 +270,9 @@ int prepare(hot_ctx* c, const hot_slm* slm, int B, const int32_t* counts, const 
     // 512-thread blocks: the pixel pass reuses each trap record twice)
     P.q = (c->tune_q == 0 && P.fg.seg_w > 256) ? 2 : q;
     P.nt = P.fg.seg_w <= 256 * P.q ? 256 : 512;
+    // one row per block: two rows sharing an update and one set of trap-sum additions were
+    // measured slower (GSW 512^2 x 100: 18.8 against 18.0 us per iteration)
+    P.rows = P.nt == 256 && c->tune_rows > 0 ? c->tune_rows : 1;
   }
   P.fgf = row_segments(slm->nx, slm->ny, c->tune_seg > 0 ? c->tune_seg : kSegMax);
   P.nblk_stored = stored_nblk(P.n);
@@ -456,6 +459,7 @@ IterArgs iter_args(hot_ctx* c, const Plan& P, float* phase, int K) {
   a.nt = P.nt;
   a.q = P.q;
   a.tpl = P.tpl;
+  a.rows = P.rows;
   if (P.B == 1) a.one = c->h_hd[0];
   a.fract = P.fract;
   a.coef = (const TrapCoef*)c->coef.p;
@@ -545,7 +549,8 @@ int solve(hot_ctx* c, const hot_slm* slm, int B, const int32_t* counts, const do
   if (c->use_graphs) {
     std::vector<uint64_t> key = {(uint64_t)B, (uint64_t)P.T, (uint64_t)P.nx, (uint64_t)P.ny, (uint64_t)K,
                                  (uint64_t)algo, (uint64_t)variant, (uint64_t)P.fract, (uint64_t)P.nt, (uint64_t)P.q,
-                                 (uint64_t)P.tpl, (uint64_t)P.fg.seg_w, (uint64_t)P.sep_w, (uint64_t)P.sep_sc, (uint64_t)(uintptr_t)phase,
+                                 (uint64_t)P.tpl, (uint64_t)P.fg.seg_w, (uint64_t)P.sep_w, (uint64_t)P.sep_sc,
+                                 (uint64_t)P.rows, (uint64_t)(uintptr_t)phase,
                                  (uint64_t)(uintptr_t)V, (uint64_t)(uintptr_t)w_out, (uint64_t)(uintptr_t)theta_out,
                                  (uint64_t)(uintptr_t)c->coef.p, (uint64_t)(uintptr_t)c->st.p,
                                  (uint64_t)(uintptr_t)c->hd.p, (uint64_t)(uintptr_t)c->partial.p,
@@ -724,6 +729,10 @@ int hot_set_tuning(hot_ctx* c, int key, int value) {
       if (value < 0 || value > HOT_MAX_TRAPS || value % 16 != 0)
         return fail(HOT_EINVAL, "separable chunk must be 0 or a multiple of 16 up to %d", HOT_MAX_TRAPS);
       c->tune_sepc = value;
+      return HOT_OK;
+    case HOT_TUNE_ROWS:
+      if (value != 0 && value != 1 && value != 2) return fail(HOT_EINVAL, "rows per block must be 0, 1 or 2");
+      c->tune_rows = value;
       return HOT_OK;
     case HOT_TUNE_SLICES:
       if (value < 0 || value > 16) return fail(HOT_EINVAL, "slices must be 0..16");

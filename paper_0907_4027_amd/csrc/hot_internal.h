@@ -64,7 +64,8 @@ constexpr int kAccRegions = 8;
 struct IterArgs {
   FwdGeom fg;
   int B = 1;
-  int nt = 256, q = 1, tpl = 1;  // block threads (256/512), pixels per lane (1/2), traps per lane
+  int nt = 256, q = 1, tpl = 1;  // threads per row (256/512), pixels per lane (1/2), traps per lane
+  int rows = 1;                  // rows per block: 1, or 2 (nt = 256 only)
   HoloDesc one{};                // B == 1: the hologram's descriptor (one.m > 0), passed by value
   bool fract = false;
   const TrapCoef* coef = nullptr;

@@ -342,11 +342,15 @@ __device__ __forceinline__ LaneCoef<TPL> load_lane_coef(const TrapCoef* __restri
 
 // `first` holds the lane's coefficients of the first chunk (k0 = 0), loaded by the caller before
 // its own global stores, so that waiting for them does not wait for those stores too.
-template <int W, int TPL, bool FRACT, class Store>
+// With ROWS = 2 the block is two halves of W waves, each passing over its own row (px, len, Vr
+// of the calling thread's half); the slice partials of both rows are summed together, so
+// store(m, sum) gets the block's sum over both rows.
+template <int W, int TPL, bool FRACT, int ROWS, class Store>
 __device__ __forceinline__ void trap_pass_block(const TrapCoef* __restrict__ cf, int M, int G, int A, float Vr,
                                                 float V2, const float4* px, int len, float2* red, Store store,
                                                 const LaneCoef<TPL>& first) {
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int half = (int)threadIdx.x / (W * 64);
+  const int wave = ((int)threadIdx.x >> 6) - half * W, lane = threadIdx.x & 63;
   const int s = lane / G, tl = lane - s * G;
   const bool active = s < A;
   const int S = W * A;
@@ -419,14 +423,14 @@ __device__ __forceinline__ void trap_pass_block(const TrapCoef* __restrict__ cf,
     __syncthreads();  // red[] is free: earlier readers (previous chunk, or the pixel pass) are done
     if (active) {
 #pragma unroll
-      for (int k = 0; k < TPL; ++k) red[sidx * nslot + tl + k * G] = make_float2(accr[k], acci[k]);
+      for (int k = 0; k < TPL; ++k) red[(half * S + sidx) * nslot + tl + k * G] = make_float2(accr[k], acci[k]);
     }
     __syncthreads();
-    for (int i = threadIdx.x; i < nslot; i += W * 64) {
+    for (int i = threadIdx.x; i < nslot; i += ROWS * W * 64) {
       const int m = k0 + i;
       if (m < M) {
         float2 acc = make_float2(0.0f, 0.0f);
-        for (int s2 = 0; s2 < S; ++s2) {
+        for (int s2 = 0; s2 < ROWS * S; ++s2) {
           const float2 v = red[s2 * nslot + i];
           acc.x += v.x;
           acc.y += v.y;
@@ -439,7 +443,9 @@ __device__ __forceinline__ void trap_pass_block(const TrapCoef* __restrict__ cf,
 
 // ------------------------------------------------------------------ fused iteration kernel
 //
-// Grid (nseg, ny, B), NT threads, one row segment (seg_w <= NT * Q pixels) per block.
+// Grid (nseg, ceil(ny / ROWS), B), ROWS * NT threads.  Each half of NT threads passes over one row
+// segment (seg_w <= NT * Q pixels) of row ROWS * blockIdx.y + half; both halves share the update
+// and add one sum per trap (ROWS = 2 halves the update work and the atomic adds per row).
 //   upd = 0: use st_in as is;  1/2: GS/GSW update from V of the previous mask and st_in,
 //   recomputed by every block; block (0, 0, b) also writes the new state to st_out and the
 //   figures of merit of that V to stats[b][kstat].
@@ -453,29 +459,33 @@ __device__ __forceinline__ void trap_pass_block(const TrapCoef* __restrict__ cf,
 //   The arguments the first loads need lead the list (they fit the SGPRs that the kernel
 //   arguments are preloaded into at wave launch).
 // Writes phase (radians).
-template <int NT, int Q, int TPL, bool FRACT>
-__global__ void __launch_bounds__(NT)
+template <int NT, int Q, int TPL, bool FRACT, int ROWS>
+__global__ void __launch_bounds__(NT * ROWS)
 k_iter(HoloDesc one, const TrapCoef* __restrict__ coef, const TrapState* __restrict__ st_in,
        const ulonglong2* __restrict__ acc_in, const HoloDesc* __restrict__ hd, TrapState* __restrict__ st_out,
        ulonglong2* __restrict__ acc_out, ulonglong2* __restrict__ acc_zero, int T, float scale, float unscale,
        float* __restrict__ stats, int kstat, int stat_stride, int upd, int* __restrict__ flag, int nx, int ny,
        int seg_w, float* __restrict__ phase) {
-  constexpr int W = NT / 64;
+  constexpr int W = NT / 64;        // waves per half
+  constexpr int NB = NT * ROWS;     // threads of the block
   constexpr int PXN = NT * Q + 136;  // slices cover < len + S <= len + 128 entries, plus 3 read ahead
-  constexpr int REDN = W * 64 * TPL;                   // float2 slice partials
-  constexpr int RECN = rec_pad(kMaxTraps);             // float4 pixel-pass records
-  constexpr int UN = 2 * RECN > REDN ? 2 * RECN : REDN;  // in float2 units
-  __shared__ float4 px[PXN];
-  __shared__ float2 ubuf[UN];  // pixel-pass records, then slice partials in the trap pass
-  __shared__ float sh[8 * W];
-  const int b = blockIdx.z, r = blockIdx.y, sg = blockIdx.x;
+  constexpr int REDN = ROWS * W * 64 * TPL;            // float2 slice partials of both halves
+  constexpr int RECN = rec_pad(kMaxTraps);             // float4 pixel-pass records of one row
+  constexpr int UN = 2 * ROWS * RECN > REDN ? 2 * ROWS * RECN : REDN;  // in float2 units
+  __shared__ float4 pxs[ROWS * PXN];
+  __shared__ float2 ubuf[UN];  // pixel-pass records (one set per row), then slice partials
+  __shared__ float sh[8 * NB / 64];
+  const int b = blockIdx.z, sg = blockIdx.x;
+  const int half = ROWS == 1 ? 0 : (int)threadIdx.x / NT, tid = (int)threadIdx.x - half * NT;
+  const int r = blockIdx.y * ROWS + half;
   const HoloDesc d = one.m > 0 ? one : hd[b];
   const int M = d.m, off = d.off, G = d.g, A = d.a;
   const TrapCoef* __restrict__ cf = coef + off;
   const float Vr = (float)(2 * r - (ny - 1));
   const float V2 = Vr * Vr;
-  float4* rec = reinterpret_cast<float4*>(ubuf);
-  const bool lead = sg == 0 && r == 0;
+  float4* rec_all = reinterpret_cast<float4*>(ubuf);
+  float4* px = pxs + half * PXN;
+  const bool lead = sg == 0 && blockIdx.y == 0;
   const VAcc vacc{acc_in, T, off, unscale};
 
   // Every read of the block's own trap data is issued here, unconditionally (threads past M read
@@ -486,44 +496,50 @@ k_iter(HoloDesc one, const TrapCoef* __restrict__ coef, const TrapState* __restr
   const float2 v_first = vacc(tm);
   const LaneCoef<TPL> lane_first = load_lane_coef<TPL>(cf, M, G, 0, Vr, V2);
   if (lead) {
-    for (int i = threadIdx.x; i < kAccRegions * M; i += NT) {
+    for (int i = threadIdx.x; i < kAccRegions * M; i += NB) {
       const int g = i / M;
       acc_zero[(size_t)g * T + off + (i - g * M)] = make_ulonglong2(0ull, 0ull);
     }
   }
   auto coef_of = [&](int m) { return m == (int)threadIdx.x ? c_first : cf[m]; };
-  if (upd == 0) {
-    for (int m = threadIdx.x; m < M; m += NT) {
-      const TrapState s = m == (int)threadIdx.x ? s_first : st_in[off + m];
-      stage_record<NT>(rec, coef_of(m), Vr, V2, s.theta_rev, s.w, m);
+  // records of trap m for every row of the block
+  auto stage = [&](int m, const TrapCoef& c, const TrapState& s) {
+#pragma unroll
+    for (int h = 0; h < ROWS; ++h) {
+      const float vr = (float)(2 * (int)(blockIdx.y * ROWS + h) - (ny - 1));
+      stage_record<NT>(rec_all + h * RECN, c, vr, vr * vr, s.theta_rev, s.w, m);
     }
+  };
+  if (upd == 0) {
+    for (int m = threadIdx.x; m < M; m += NB) stage(m, coef_of(m), m == (int)threadIdx.x ? s_first : st_in[off + m]);
   } else {
     auto emit = [&](int m, const TrapState& s) {
       if (lead) st_out[off + m] = s;
-      stage_record<NT>(rec, coef_of(m), Vr, V2, s.theta_rev, s.w, m);
+      stage(m, coef_of(m), s);
     };
-    update_traps<NT, VAcc, decltype(emit), true>(vacc, st_in, off, M, upd, sh,
+    update_traps<NB, VAcc, decltype(emit), true>(vacc, st_in, off, M, upd, sh,
                                                  lead ? stats + 3 * ((size_t)b * stat_stride + kstat) : nullptr,
                                                  lead ? flag : nullptr, emit, v_first, s_first);
   }
-  pad_records<NT>(rec, M);
+#pragma unroll
+  for (int h = 0; h < ROWS; ++h) pad_records<NB>(rec_all + h * RECN, M);
   __syncthreads();
 
   const int cbeg = sg * seg_w;
-  const int len = min(nx, cbeg + seg_w) - cbeg;
+  const int len = r < ny ? min(nx, cbeg + seg_w) - cbeg : 0;  // a missing last row has no pixels
   float U[Q], U2[Q], sr[Q], si[Q];
 #pragma unroll
   for (int q = 0; q < Q; ++q) {
-    U[q] = (float)(2 * (cbeg + (int)threadIdx.x + q * NT) - (nx - 1));
+    U[q] = (float)(2 * (cbeg + tid + q * NT) - (nx - 1));
     U2[q] = U[q] * U[q];
     sr[q] = 0.0f;
     si[q] = 0.0f;
   }
-  pixel_terms<Q, FRACT>(rec, M, U, U2, sr, si);
+  pixel_terms<Q, FRACT>(rec_all + half * RECN, M, U, U2, sr, si);
   float* __restrict__ prow = phase + (size_t)b * nx * ny + (size_t)r * nx + cbeg;
 #pragma unroll
   for (int q = 0; q < Q; ++q) {
-    const int i = threadIdx.x + q * NT;
+    const int i = tid + q * NT;
     if (i < len) {
       const float ph = phase_of(si[q], sr[q]);
       prow[i] = ph;
@@ -532,7 +548,7 @@ k_iter(HoloDesc one, const TrapCoef* __restrict__ coef, const TrapState* __restr
       px[i] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
     }
   }
-  for (int i = NT * Q + threadIdx.x; i < PXN; i += NT) px[i] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+  for (int i = NT * Q + tid; i < PXN; i += NT) px[i] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
   __syncthreads();
   ulonglong2* __restrict__ mine = acc_out + (size_t)(xcc_id() & (kAccRegions - 1)) * T + off;
   auto add_sum = [&](int m, float2 v) {
@@ -542,7 +558,7 @@ k_iter(HoloDesc one, const TrapCoef* __restrict__ coef, const TrapState* __restr
     __hip_atomic_fetch_add(p + 1, (unsigned long long)(long long)(v.y * scale), __ATOMIC_RELAXED,
                            __HIP_MEMORY_SCOPE_AGENT);
   };
-  trap_pass_block<W, TPL, FRACT>(cf, M, G, A, Vr, V2, px, len, ubuf, add_sum, lane_first);
+  trap_pass_block<W, TPL, FRACT, ROWS>(cf, M, G, A, Vr, V2, px, len, ubuf, add_sum, lane_first);
 }
 
 // ------------------------------------------------------------------ stand-alone passes
@@ -630,7 +646,7 @@ k_forward(const TrapCoef* __restrict__ coef, const HoloDesc* __restrict__ hd, co
   __syncthreads();
   const int nblk = ny * nseg;
   float2* __restrict__ out = partial + (size_t)off * nblk + r * nseg + sg;
-  trap_pass_block<W, TPL, FRACT>(coef + off, M, G, A, Vr, Vr * Vr, px, len, red,
+  trap_pass_block<W, TPL, FRACT, 1>(coef + off, M, G, A, Vr, Vr * Vr, px, len, red,
                                  [&](int m, float2 v) { out[(size_t)m * nblk] = v; }, lane_first);
 }
 
@@ -1177,15 +1193,24 @@ __global__ void k_import_w(const float* __restrict__ w0, TrapState* __restrict__
 
 // ------------------------------------------------------------------ template dispatch
 
-template <int NT, int Q, int TPL, bool FRACT>
-hipError_t iter_t(hipStream_t s, const IterArgs& a) {
+template <int NT, int Q, int TPL, bool FRACT, int ROWS>
+hipError_t iter_rows(hipStream_t s, const IterArgs& a) {
   if (a.fg.seg_w > NT * Q || !a.acc_in || !a.acc_out || !a.acc_zero || a.T < 1) return hipErrorInvalidValue;
-  dim3 grid(a.fg.nseg, a.fg.ny, a.B);
-  hipLaunchKernelGGL((k_iter<NT, Q, TPL, FRACT>), grid, dim3(NT), 0, s, a.B == 1 ? a.one : HoloDesc{}, a.coef,
+  dim3 grid(a.fg.nseg, (a.fg.ny + ROWS - 1) / ROWS, a.B);
+  hipLaunchKernelGGL((k_iter<NT, Q, TPL, FRACT, ROWS>), grid, dim3(NT * ROWS), 0, s, a.B == 1 ? a.one : HoloDesc{}, a.coef,
                      a.st_in, (const ulonglong2*)a.acc_in, a.hd, a.st_out, (ulonglong2*)a.acc_out,
                      (ulonglong2*)a.acc_zero, a.T, a.acc_scale, a.acc_unscale, a.stats, a.kstat, a.stat_stride,
                      a.upd, a.flag, a.fg.nx, a.fg.ny, a.fg.seg_w, a.phase);
   return hipGetLastError();
+}
+
+template <int NT, int Q, int TPL, bool FRACT>
+hipError_t iter_t(hipStream_t s, const IterArgs& a) {
+  if constexpr (NT == 256) {
+    if (a.rows == 2) return iter_rows<NT, Q, TPL, FRACT, 2>(s, a);
+  }
+  if (a.rows != 1) return hipErrorInvalidValue;
+  return iter_rows<NT, Q, TPL, FRACT, 1>(s, a);
 }
 
 template <int NT, int Q, bool FRACT>

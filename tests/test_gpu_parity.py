@@ -213,6 +213,37 @@ def test_batched_equals_plain_and_oracle(ctx):
             assert_V(V[o[b]:o[b + 1]], ref["V"])
 
 
+@pytest.mark.parametrize("algo,nx,ny,m", [("gsw", 200, 91, 37), ("gs", 256, 64, 100), ("rs", 130, 33, 9)])
+def test_two_rows_per_block(hot, algo, nx, ny, m):
+    """Blocks of two rows (one shared update, one set of trap-sum additions per block) give the
+    oracle's answer; an odd row count leaves the last block's second half without a row."""
+    p = W.random_problem(440 + ny, nx, ny, m, 6)
+    with hot.Context(0) as c:
+        c.set_tuning(rows=2)
+        g = run(c, algo, p)
+    o = oracle_solve(algo, p, p.iters)
+    assert_phase(to_np(g.phase), o["phi"])
+    assert_V(to_np(g.V), o["V"])
+    assert_stats(g.stats, o["stats"])
+
+
+def test_two_rows_per_block_batched(hot):
+    """Batched holograms with uneven trap counts in two-row blocks match one-row blocks."""
+    bt = W.c4(6)
+    bt.iters = 6
+    with hot.Context(0) as c1, hot.Context(0) as c2:
+        c2.set_tuning(rows=2)
+        r1 = c1.hot_gsw_batched(bt.slm, bt.counts, bt.xyz, bt.theta0, bt.iters)
+        r2 = c2.hot_gsw_batched(bt.slm, bt.counts, bt.xyz, bt.theta0, bt.iters)
+        torch.cuda.synchronize()
+    ph1, ph2 = to_np(r1.phase), to_np(r2.phase)
+    for b in range(bt.b):
+        assert_phase(ph2[b], ph1[b], what=f"two rows vs one row, hologram {b}")
+    assert_V(to_np(r2.V), as_complex(to_np(r1.V)), what="two rows vs one row")
+    for b in range(bt.b):
+        assert_stats(r2.stats[b], r1.stats[b])
+
+
 # ------------------------------------------------------------------ stored exp(i Delta) variant
 
 @pytest.mark.parametrize("algo", ["rs", "gsw"])
