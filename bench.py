@@ -238,11 +238,19 @@ def main():
         plain_fa()
         tb = time_calls(batched_fa, 10, sync)
         tp = time_calls(plain_fa, 10, sync)
+        # the plain form is 16 C-ABI calls per step: its time depends on the host as much as on the GPU
+        sync()
+        h0 = time.perf_counter()
+        for _ in range(10):
+            plain_fa()
+        host_ms = (time.perf_counter() - h0) / 10 * 1e3
+        sync()
         upd = bt.slm.n * T
         out["adjoint"] = {"workload": f"{bt.name}: forward V + adjoint dL/dphi, 8 x 512^2 x 64 traps",
                           "ms": round(tb, 4), "updates_per_s": upd / (tb * 1e-3), "plain_ms": round(tp, 4),
-                          "plain_updates_per_s": upd / (tp * 1e-3), "speedup_vs_plain": round(tp / tb, 3)}
-        log(f"[bench] forward+adjoint batched {tb:.4f} ms vs plain {tp:.4f} ms")
+                          "plain_updates_per_s": upd / (tp * 1e-3), "speedup_vs_plain": round(tp / tb, 3),
+                          "plain_host_enqueue_ms": round(host_ms, 4)}
+        log(f"[bench] forward+adjoint batched {tb:.4f} ms vs plain {tp:.4f} ms (plain host enqueue {host_ms:.4f} ms)")
 
     # ---------------------------------------------------------------- stored exp(i Delta) variant (HBM-bound)
     if not args.no_extra and args.only in (None, "stored"):
