@@ -196,8 +196,8 @@ int hot_encode_u8(hot_ctx* ctx, int64_t n, const float* phase, uint8_t* frame);
  *          kernel, which also sums the trap pass into V's fixed-point accumulators; separable:
  *          the fused update + both passes on the matrix cores; stored: the pixel and trap
  *          pass kernels)
- *   ms[1]  the reduction into V (stored and separable: of the per-block partials, once per
- *          iteration; on-the-fly: of the fixed-point accumulators, once per solve)
+ *   ms[1]  the reduction into V (stored: of the per-block partials, once per iteration;
+ *          on-the-fly and separable: of the fixed-point accumulators, once per solve)
  *   ms[2]  the pixel pass alone   ms[3]  the trap pass alone
  * phase (device, N floats) and V (device, 2M floats) are scratch outputs.  Synchronises
  * the stream. */

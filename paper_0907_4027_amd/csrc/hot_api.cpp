@@ -440,10 +440,13 @@ SepArgs sep_args(hot_ctx* c, const Plan& P, int mode, float* phase, int K) {
   a.inv_n = (float)(1.0 / (double)P.n);
   a.phase = phase;
   a.partial = (float2*)c->partial.p;
+  a.T = P.T;
+  a.acc_scale = P.acc_scale;
+  a.acc_unscale = P.acc_unscale;
   return a;
 }
 
-// Buffer i (0..2) of the direct path's rotating fixed-point sums.
+// Buffer i (0..2) of the iteration kernels' rotating fixed-point sums.
 unsigned long long* acc_buf(hot_ctx* c, const Plan& P, int i) {
   return (unsigned long long*)c->acc.p + (size_t)i * 2 * kAccRegions * P.T;
 }
@@ -483,10 +486,10 @@ int solve(hot_ctx* c, const hot_slm* slm, int B, const int32_t* counts, const do
   const bool separable = variant == HOT_SEPARABLE;
   const int nblk = stored ? P.nblk_stored : separable ? P.nblk_sep : P.fg.nblk();
   if ((rc = upload_tables(c, slm, P, xyz, counts))) return rc;
-  if ((stored || separable) && (rc = ensure(c, c->partial, sizeof(float2) * (size_t)P.T * nblk))) return rc;
+  if (stored && (rc = ensure(c, c->partial, sizeof(float2) * (size_t)P.T * nblk))) return rc;
   if ((rc = ensure(c, c->stats, sizeof(float) * 3 * (size_t)B * (K + 1)))) return rc;
   if (stored && (rc = ensure_stored(c, P))) return rc;
-  if (!stored && !separable && (rc = ensure_acc(c, P))) return rc;
+  if (!stored && (rc = ensure_acc(c, P))) return rc;
   TrapState* st[2] = {(TrapState*)c->st.p, (TrapState*)c->st.p + P.T};
   if (w0) HIP_TRY(launch_import_w(c->stream, w0, st[0], P.T));
 
@@ -500,17 +503,21 @@ int solve(hot_ctx* c, const hot_slm* slm, int B, const int32_t* counts, const do
   auto enqueue = [&](hipStream_t s) -> hipError_t {
     hipError_t e = hipSuccess;
     if (separable) {
+      // one launch per iteration, with the same rotation of fixed-point sums as the direct path
       SepArgs a = sep_args(c, P, 0, phase, K);
+      e = launch_fill_u32(s, (unsigned*)acc_buf(c, P, 1), 0u, 4 * kAccRegions * P.T);
       for (int k = 0; k <= K && e == hipSuccess; ++k) {
         a.upd = k == 0 ? 0 : upd;
         a.st_in = k == 0 ? st[0] : st[(k - 1) & 1];
         a.st_out = st[k & 1];
-        a.vin = V;
+        a.acc_in = acc_buf(c, P, k % 3);
+        a.acc_out = acc_buf(c, P, (k + 1) % 3);
+        a.acc_zero = acc_buf(c, P, (k + 2) % 3);
         a.kstat = k - 1;
         a.phase = k == K ? phase : nullptr;  // only the last mask's phase is returned
         e = launch_sep(s, a);
-        if (e == hipSuccess) e = launch_reduce(s, B, P.mmax, nblk, inv_n, part, hd, V);
       }
+      if (e == hipSuccess) e = launch_collect(s, P.T, acc_buf(c, P, (K + 1) % 3), P.acc_unscale, V);
     } else if (!stored) {
       // one launch per iteration: launch k reads buffer k % 3, adds into (k + 1) % 3 (buffer 1 is
       // cleared first, the others by the launches) and clears (k + 2) % 3
@@ -871,30 +878,29 @@ int hot_time_passes(hot_ctx* c, const hot_slm* slm, int32_t M, const double* xyz
   if ((rc = ensure(c, c->partial, sizeof(float2) * (size_t)P.T * nblk))) return rc;
   if ((rc = ensure(c, c->stats, sizeof(float) * 3 * 2))) return rc;
   if (stored && (rc = ensure_stored(c, P))) return rc;
-  if (!stored && !separable && (rc = ensure_acc(c, P))) return rc;
+  if (!stored && (rc = ensure_acc(c, P))) return rc;
   const TrapCoef* coef = (const TrapCoef*)c->coef.p;
   TrapState* st[2] = {(TrapState*)c->st.p, (TrapState*)c->st.p + P.T};
   const HoloDesc* hd = (const HoloDesc*)c->hd.p;
   float2* part = (float2*)c->partial.p;
   const float inv_n = (float)(1.0 / (double)P.n);
-  // group 0: one GSW iteration's main kernel (fused passes, or the stored pixel + trap pass).
-  // The fused kernel reads buffer 0 (filled beforehand by a pass over the theta0 mask), adds
-  // into buffer 1 (its sums then wrap around over the repetitions: integers, and unused) and
-  // clears buffer 2.
+  // group 0: one GSW iteration's main kernel (the fused on-the-fly or separable kernel, or the
+  // stored pixel + trap pass).  A fused kernel reads buffer 0 (filled beforehand by a pass over
+  // the theta0 mask), adds into buffer 1 (its sums then wrap around over the repetitions:
+  // integers, and unused) and clears buffer 2.
   IterArgs a = iter_args(c, P, phase, 1);
   a.upd = 2;
   a.st_in = st[0];
   a.st_out = st[1];
-  if (!stored && !separable) {
-    a.acc_in = acc_buf(c, P, 0);
-    a.acc_out = acc_buf(c, P, 1);
-    a.acc_zero = acc_buf(c, P, 2);
-  }
   SepArgs sa = sep_args(c, P, 0, phase, 1);
   sa.upd = 2;
   sa.st_in = st[0];
   sa.st_out = st[1];
-  sa.vin = V;
+  if (!stored) {
+    a.acc_in = sa.acc_in = acc_buf(c, P, 0);
+    a.acc_out = sa.acc_out = acc_buf(c, P, 1);
+    a.acc_zero = sa.acc_zero = acc_buf(c, P, 2);
+  }
   auto sep_mode = [&](int mode) {
     SepArgs x = sa;
     x.mode = mode;
@@ -909,22 +915,32 @@ int hot_time_passes(hot_ctx* c, const hot_slm* slm, int32_t M, const double* xyz
     if (e != hipSuccess) return e;
     return launch_forward_stored(c->stream, P.n, 1, (const float2*)c->amat.p, (const float2*)c->efield.p, hd, part);
   };
-  // group 1: the reduction to V (per iteration on the stored and separable paths; once per solve,
-  // from the fixed-point sums, on the direct path)
+  // group 1: the reduction to V (per iteration on the stored path; once per solve, from the
+  // fixed-point sums, on the fused paths)
   auto g1 = [&]() {
-    if (!stored && !separable) return launch_collect(c->stream, P.T, acc_buf(c, P, 0), P.acc_unscale, V);
-    return launch_reduce(c->stream, 1, P.mmax, stored ? P.nblk_stored : P.nblk_sep, inv_n, part, hd, V);
+    if (!stored) return launch_collect(c->stream, P.T, acc_buf(c, P, 0), P.acc_unscale, V);
+    return launch_reduce(c->stream, 1, P.mmax, P.nblk_stored, inv_n, part, hd, V);
   };
-  // the direct path's buffer 0: sums of the theta0 mask (a pass without update)
+  // a fused path's buffer 0: sums of the theta0 mask (a pass without update)
   auto prime = [&]() -> hipError_t {
-    if (stored || separable) return hipSuccess;
+    if (stored) return hipSuccess;
+    hipError_t e = launch_fill_u32(c->stream, (unsigned*)acc_buf(c, P, 0), 0u, 4 * kAccRegions * P.T);
+    if (e != hipSuccess) return e;
+    if (separable) {
+      SepArgs p0 = sa;
+      p0.upd = 0;
+      p0.phase = nullptr;
+      p0.acc_in = acc_buf(c, P, 2);
+      p0.acc_out = acc_buf(c, P, 0);
+      p0.acc_zero = acc_buf(c, P, 1);
+      return launch_sep(c->stream, p0);
+    }
     IterArgs p0 = a;
     p0.upd = 0;
     p0.acc_in = acc_buf(c, P, 2);
     p0.acc_out = acc_buf(c, P, 0);
     p0.acc_zero = acc_buf(c, P, 1);
-    hipError_t e = launch_fill_u32(c->stream, (unsigned*)acc_buf(c, P, 0), 0u, 4 * kAccRegions * P.T);
-    return e == hipSuccess ? launch_iter(c->stream, p0) : e;
+    return launch_iter(c->stream, p0);
   };
   auto g2 = [&]() {
     if (separable) return sep_mode(2);

@@ -130,7 +130,13 @@ struct SepArgs {
   const HoloDesc* hd = nullptr;
   const TrapState* st_in = nullptr;
   TrapState* st_out = nullptr;
-  const float* vin = nullptr;  // V of the previous mask (mode 0 with upd != 0) or G (mode 3), interleaved
+  const float* vin = nullptr;  // G (mode 3), interleaved
+  // mode 0: rotating fixed-point trap sums, as for the direct iteration kernel
+  const unsigned long long* acc_in = nullptr;
+  unsigned long long* acc_out = nullptr;
+  unsigned long long* acc_zero = nullptr;
+  int T = 0;
+  float acc_scale = 0.0f, acc_unscale = 0.0f;
   float* stats = nullptr;
   int kstat = 0, stat_stride = 1;
   int upd = 0;  // mode 0: 0 none, 1 GS, 2 GSW
@@ -138,7 +144,7 @@ struct SepArgs {
   float inv_n = 0.0f;
   float* phase = nullptr;  // mode 0: written when non-null; modes 1, 3: read; mode 2: written
   float* grad = nullptr;
-  float2* partial = nullptr;  // [T][nblk()]
+  float2* partial = nullptr;  // mode 1: [T][nblk()]
   int gx() const { return (nx + 16 * W - 1) / (16 * W); }
   int gy() const { return (ny + 15) / 16; }
   int nblk() const { return gx() * gy(); }

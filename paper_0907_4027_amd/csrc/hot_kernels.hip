@@ -923,8 +923,11 @@ __device__ __forceinline__ void trap_tiles(const float2* xc, const float2* yc, i
   }
 }
 
-// MODE 0: one iteration: update, pixel pass, trap-pass partials (phase written when non-null)
-// MODE 1: trap pass alone from the given phase (Eq. 1)
+// MODE 0: one iteration: update, pixel pass, trap pass (phase written when non-null).  As in k_iter,
+//   V of the previous mask is the sum of acc_in's per-XCD fixed-point regions, each trap's block
+//   sum is added to acc_out's region of the adding wave's XCD, and block (0, 0, b) clears
+//   hologram b's part of acc_zero; acc_in is read even when upd == 0 (a valid buffer).
+// MODE 1: trap pass alone from the given phase (Eq. 1): per-block partials
 // MODE 2: pixel pass alone from the given state (phase out)
 // MODE 3: adjoint of Eq. 1: weights G_m (vin), grad[j] = (1/N) Im(e^{-i phi_j} S_j) for the given phase
 // Grid (ceil(nx / 16 W), ceil(ny / 16), B); sc = traps per super-chunk (a multiple of 16);
@@ -934,7 +937,9 @@ __global__ void __launch_bounds__(W * 64)
 k_sep(const TrapCoef* __restrict__ coef, const HoloDesc* __restrict__ hd, const TrapState* __restrict__ st_in,
       TrapState* __restrict__ st_out, const float* __restrict__ vin, float* __restrict__ stats, int kstat,
       int stat_stride, int upd, int* __restrict__ flag, int nx, int ny, float inv_n, int sc,
-      float* __restrict__ phase, float* __restrict__ grad, float2* __restrict__ partial) {
+      float* __restrict__ phase, float* __restrict__ grad, float2* __restrict__ partial,
+      const ulonglong2* __restrict__ acc_in, ulonglong2* __restrict__ acc_out, ulonglong2* __restrict__ acc_zero,
+      int T, float scale, float unscale) {
   constexpr int NT = W * 64, CW = 16 * W;
   constexpr bool kPixel = MODE != 1, kTrap = MODE <= 1;
   extern __shared__ float4 lds4[];
@@ -1005,6 +1010,8 @@ k_sep(const TrapCoef* __restrict__ coef, const HoloDesc* __restrict__ hd, const 
   // per-trap coefficients into LDS.  Trap threadIdx.x's coefficients, V and state are loaded
   // first; the block then builds the first super-chunk's X table (which needs no weights) while
   // the update's inputs arrive, and only then does the GS/GSW update.
+  const VAcc vacc{acc_in, T, off, unscale};
+  const bool lead = blockIdx.x == 0 && blockIdx.y == 0;
   TrapCoef c_first = {0.0f, 0.0f, 0.0f, 0.0f};
   float2 v_first = make_float2(0.0f, 0.0f);
   TrapState s_first = {0.0f, 0.0f, 0.0f, 0.0f};
@@ -1012,7 +1019,13 @@ k_sep(const TrapCoef* __restrict__ coef, const HoloDesc* __restrict__ hd, const 
     c_first = coef[off + threadIdx.x];
     if (kPixel && MODE != 3) {
       s_first = st_in[off + threadIdx.x];
-      if (MODE == 0 && upd != 0) v_first = make_float2(vin[2 * (off + threadIdx.x)], vin[2 * (off + threadIdx.x) + 1]);
+      if (MODE == 0 && upd != 0) v_first = vacc(threadIdx.x);
+    }
+  }
+  if (MODE == 0 && lead) {
+    for (int i = threadIdx.x; i < kAccRegions * M; i += NT) {
+      const int gi = i / M;
+      acc_zero[(size_t)gi * T + off + (i - gi * M)] = make_ulonglong2(0ull, 0ull);
     }
   }
   for (int m = NT + (int)threadIdx.x; m < Mp; m += NT) {
@@ -1032,14 +1045,13 @@ k_sep(const TrapCoef* __restrict__ coef, const HoloDesc* __restrict__ hd, const 
     } else if (MODE == 2 || upd == 0) {
       for (int m = threadIdx.x; m < M; m += NT) cw[m] = trap_weight(m == (int)threadIdx.x ? s_first : st_in[off + m]);
     } else {
-      const bool lead = blockIdx.x == 0 && blockIdx.y == 0;
       auto emit = [&](int m, const TrapState& st) {
         if (lead) st_out[off + m] = st;
         cw[m] = trap_weight(st);
       };
-      update_traps<NT, VArray, decltype(emit), true>(VArray{vin, off}, st_in, off, M, upd, sh,
-                                                     lead ? stats + 3 * ((size_t)b * stat_stride + kstat) : nullptr,
-                                                     lead ? flag : nullptr, emit, v_first, s_first);
+      update_traps<NT, VAcc, decltype(emit), true>(vacc, st_in, off, M, upd, sh,
+                                                   lead ? stats + 3 * ((size_t)b * stat_stride + kstat) : nullptr,
+                                                   lead ? flag : nullptr, emit, v_first, s_first);
     }
     for (int m = M + (int)threadIdx.x; m < Mp; m += NT) cw[m] = make_float2(0.0f, 0.0f);
     __syncthreads();
@@ -1155,7 +1167,16 @@ k_sep(const TrapCoef* __restrict__ coef, const HoloDesc* __restrict__ hd, const 
           acc.x += red[w * sc + m].x;
           acc.y += red[w * sc + m].y;
         }
-        partial[(size_t)(off + k0 + m) * nblk + blk] = acc;
+        if constexpr (MODE == 0) {
+          unsigned long long* p =
+              reinterpret_cast<unsigned long long*>(acc_out + (size_t)(xcc_id() & (kAccRegions - 1)) * T + off + k0 + m);
+          __hip_atomic_fetch_add(p, (unsigned long long)(long long)(acc.x * scale), __ATOMIC_RELAXED,
+                                 __HIP_MEMORY_SCOPE_AGENT);
+          __hip_atomic_fetch_add(p + 1, (unsigned long long)(long long)(acc.y * scale), __ATOMIC_RELAXED,
+                                 __HIP_MEMORY_SCOPE_AGENT);
+        } else {
+          partial[(size_t)(off + k0 + m) * nblk + blk] = acc;
+        }
       }
     }
   }
@@ -1353,9 +1374,11 @@ hipError_t sep_t(hipStream_t s, const SepArgs& a) {
   const size_t lds = sep_lds_bytes(W, a.sc, a.mmax);
   if (lds > (size_t)kSepLdsMax) return hipErrorInvalidValue;
   dim3 grid(a.gx(), a.gy(), a.B);
+  if (MODE == 0 && (!a.acc_in || !a.acc_out || !a.acc_zero || a.T < 1)) return hipErrorInvalidValue;
   hipLaunchKernelGGL((k_sep<W, MODE, FRACT>), grid, dim3(W * 64), lds, s, a.coef, a.hd, a.st_in, a.st_out, a.vin,
                      a.stats, a.kstat, a.stat_stride, a.upd, a.flag, a.nx, a.ny, a.inv_n, a.sc, a.phase, a.grad,
-                     a.partial);
+                     a.partial, (const ulonglong2*)a.acc_in, (ulonglong2*)a.acc_out, (ulonglong2*)a.acc_zero, a.T,
+                     a.acc_scale, a.acc_unscale);
   return hipGetLastError();
 }
 
