@@ -141,6 +141,18 @@ def test_1024sq_256_traps_sampled(ctx):
     assert_stats(g3.stats, o3["stats"])
 
 
+@pytest.mark.parametrize("n,m", [(2048, 6), (4096, 4)])
+def test_largest_grids_fixed_point_sums(ctx, n, m):
+    """The iteration kernel's 64-bit fixed-point trap sums at the largest grids (scale 2^39 at
+    2048^2, 2^37 at 4096^2, the smallest the library uses): one GS iteration, phase and V in full."""
+    p = W.random_problem(450 + n, n, n, m, 1)
+    g = run(ctx, "gs", p)
+    o = oracle_solve("gs", p, p.iters)
+    assert_phase(to_np(g.phase), o["phi"])
+    assert_V(to_np(g.V), o["V"])
+    assert_stats(g.stats, o["stats"])
+
+
 # ------------------------------------------------------------------ single passes, batches, adjoint
 
 def test_forward_V_batched_uneven(ctx):
