@@ -18,7 +18,10 @@
  *   Output     phases in [0, 2 pi] (float rounding can return 2 pi itself);
  *              V as interleaved (re, im) float pairs.
  *   Precision  FP32 on the device; per-trap coefficients are formed in FP64 on
- *              the host and rounded once.
+ *              the host and rounded once.  Inside the iterative solvers the per-block
+ *              trap sums of Eq. 1 are added as 64-bit fixed-point integers (scale
+ *              2^(61 - ceil(log2 N))), so V does not depend on the order in which
+ *              blocks finish and every run is bitwise reproducible.
  *   Ownership  the caller owns every buffer passed in and out.  "device" pointers
  *              are device memory on the context's GPU (e.g. torch data_ptr());
  *              "host" pointers are ordinary CPU memory.  The library allocates
