@@ -209,11 +209,16 @@ def main():
         tb = time_calls(batched, 3, sync)
         ts = time_calls(sequential, 2, sync)
         upd = bt.slm.n * T * bt.iters
+        # whole batched solve (31 launches of the fused kernel plus the per-solve kernels) against
+        # the issue-slot roofline: 2 terms per pixel-trap update, plus the initial pass
+        terms = 2.0 * bt.slm.n * T * (bt.iters + 1)
         out["batched"] = {"workload": f"{bt.name}: 64 x 512^2, M in [4,256] (sum {T}), 30 iterations",
                           "ms": round(tb, 3), "updates_per_s": upd / (tb * 1e-3), "holograms_per_s": bt.b / (tb * 1e-3),
                           "plain_ms": round(ts, 3), "plain_updates_per_s": upd / (ts * 1e-3),
-                          "speedup_vs_plain": round(ts / tb, 3)}
-        log(f"[bench] batched {tb:.3f} ms vs 64 plain {ts:.3f} ms")
+                          "speedup_vs_plain": round(ts / tb, 3),
+                          "frac_of_term_roofline": round(terms / (tb * 1e-3) / PEAK_TERMS_PER_S, 4)}
+        log(f"[bench] batched {tb:.3f} ms vs 64 plain {ts:.3f} ms; whole batched solve at "
+            f"{out['batched']['frac_of_term_roofline']:.3f} of the term roofline")
 
     # ---------------------------------------------------------------- adjoint: 8 x (forward + adjoint) per Adam step
     if not args.no_extra and args.only in (None, "adjoint"):

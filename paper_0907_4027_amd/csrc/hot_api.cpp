@@ -517,7 +517,6 @@ int solve(hot_ctx* c, const hot_slm* slm, int B, const int32_t* counts, const do
         a.phase = k == K ? phase : nullptr;  // only the last mask's phase is returned
         e = launch_sep(s, a);
       }
-      if (e == hipSuccess) e = launch_collect(s, P.T, acc_buf(c, P, (K + 1) % 3), P.acc_unscale, V);
     } else if (!stored) {
       // one launch per iteration: launch k reads buffer k % 3, adds into (k + 1) % 3 (buffer 1 is
       // cleared first, the others by the launches) and clears (k + 2) % 3
@@ -533,7 +532,6 @@ int solve(hot_ctx* c, const hot_slm* slm, int B, const int32_t* counts, const do
         a.kstat = k - 1;
         e = launch_iter(s, a);
       }
-      if (e == hipSuccess) e = launch_collect(s, P.T, acc_buf(c, P, (K + 1) % 3), P.acc_unscale, V);
     } else {
       for (int k = 0; k <= K && e == hipSuccess; ++k) {
         if (k > 0)
@@ -545,7 +543,11 @@ int solve(hot_ctx* c, const hot_slm* slm, int B, const int32_t* counts, const do
         if (e == hipSuccess) e = launch_reduce(s, B, P.mmax, nblk, inv_n, part, hd, V);
       }
     }
-    if (e == hipSuccess) e = launch_update(s, B, V, hd, st[K & 1], st[K & 1], dstats, K, K + 1, 0, (int*)c->flag.p);
+    // the final mask's V and figures of merit (fused paths: from the last buffer of sums)
+    if (e == hipSuccess)
+      e = stored ? launch_update(s, B, V, hd, st[K & 1], st[K & 1], dstats, K, K + 1, 0, (int*)c->flag.p)
+                 : launch_finish(s, B, P.T, acc_buf(c, P, (K + 1) % 3), P.acc_unscale, hd, st[K & 1], V, dstats, K,
+                                 K + 1);
     if (e == hipSuccess && (w_out || theta_out)) e = launch_export_state(s, st[K & 1], P.T, w_out, theta_out);
     return e;
   };

@@ -90,6 +90,11 @@ hipError_t launch_iter(hipStream_t s, const IterArgs& a);
 
 // V (2T floats, interleaved) from one buffer of the direct path's fixed-point sums.
 hipError_t launch_collect(hipStream_t s, int T, const unsigned long long* acc, float unscale, float* V);
+// End of a solve: V from the sums and its figures of merit into stats[b][kstat] (st: the final
+// state, read but not changed), one block per hologram.
+hipError_t launch_finish(hipStream_t s, int B, int T, const unsigned long long* acc, float unscale,
+                         const HoloDesc* hd, const TrapState* st, float* V, float* stats, int kstat,
+                         int stat_stride);
 
 // Pixel pass alone (Eq. 3 with weights).  mode 0 writes the phase; mode 1 (adjoint) reads
 // `phase` and G (2T floats, interleaved) and writes grad[b][j] = (1/N) Im(e^{-i phi_j} sum_m G_m e^{i Delta_j^m}).

@@ -686,6 +686,25 @@ k_collect(const ulonglong2* __restrict__ acc, int T, float unscale, float* __res
   V[2 * t + 1] = v.y;
 }
 
+// End of a solve on the fixed-point path, one block per hologram: V of its traps from the sums
+// (written to V) and their figures of merit into stats[b][kstat].
+__global__ void __launch_bounds__(256)
+k_finish(const ulonglong2* __restrict__ acc, int T, float unscale, const HoloDesc* __restrict__ hd,
+         const TrapState* __restrict__ st, float* __restrict__ V, float* __restrict__ stats, int kstat,
+         int stat_stride) {
+  __shared__ float sh[8 * 4];
+  const int b = blockIdx.x;
+  const int M = hd[b].m, off = hd[b].off;
+  const VAcc vacc{acc, T, off, unscale};
+  for (int m = threadIdx.x; m < M; m += 256) {
+    const float2 v = vacc(m);
+    V[2 * (off + m)] = v.x;
+    V[2 * (off + m) + 1] = v.y;
+  }
+  update_traps<256>(vacc, st, off, M, 0, sh, stats + 3 * ((size_t)b * stat_stride + kstat), nullptr,
+                    [](int, const TrapState&) {});
+}
+
 // One block per hologram: figures of merit of V into stats[b][kstat] and, for mode 1/2,
 // the GS/GSW update st_in -> st_out (st_out may equal st_in).
 __global__ void __launch_bounds__(256)
@@ -1325,6 +1344,14 @@ hipError_t launch_reduce(hipStream_t s, int B, int mmax, int nblk, float inv_n, 
                          const HoloDesc* hd, float* V) {
   dim3 grid((mmax + 3) / 4, B);
   hipLaunchKernelGGL(k_reduce, grid, dim3(256), 0, s, partial, hd, nblk, inv_n, V);
+  return hipGetLastError();
+}
+
+hipError_t launch_finish(hipStream_t s, int B, int T, const unsigned long long* acc, float unscale,
+                         const HoloDesc* hd, const TrapState* st, float* V, float* stats, int kstat,
+                         int stat_stride) {
+  hipLaunchKernelGGL(k_finish, dim3(B), dim3(256), 0, s, (const ulonglong2*)acc, T, unscale, hd, st, V, stats,
+                     kstat, stat_stride);
   return hipGetLastError();
 }
 
