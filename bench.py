@@ -72,6 +72,16 @@ def time_calls(fn, reps, sync):
     return e0.elapsed_time(e1) / reps
 
 
+def time_wall(fn, reps, sync):
+    """Mean wall-clock ms per call of fn over reps calls, the device synchronised before and after."""
+    sync()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        fn()
+    sync()
+    return (time.perf_counter() - t0) / reps * 1e3
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -114,6 +124,7 @@ def main():
 
     ms = None
     in_situ_ms = None
+    end_to_end_ms = None
     tuning = None
     main_ctx = ctx  # the headline runs the library's own launch shape
     if args.only in (None, "tune") and not args.no_tune:
@@ -151,6 +162,22 @@ def main():
         # correctness of what was timed: final stats from one more synchronising call
         st = main_ctx.hot_gsw(p.slm, p.xyz, p.theta0, K, phase=phase, V=V, stats=True).stats
         log(f"[bench] final e={st[-1, 0]:.4f} u={st[-1, 1]:.4f} sigma={st[-1, 2]:.4f}")
+        # end to end from the host: trap geometry in, the solve with its statistics (one stream
+        # synchronisation), the phase mask and V copied to pinned host memory
+        h_phase = torch.empty(phase.shape, dtype=phase.dtype, pin_memory=True)
+        h_V = torch.empty(V.shape, dtype=V.dtype, pin_memory=True)
+
+        def e2e():
+            main_ctx.hot_gsw(p.slm, p.xyz, p.theta0, K, phase=phase, V=V, stats=True)
+            h_phase.copy_(phase)
+            h_V.copy_(V)
+        e2e()
+        sync()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            e2e()
+        end_to_end_ms = (time.perf_counter() - t0) / args.steps * 1e3
+        log(f"[bench] end to end (host geometry in, stats sync, phase + V to pinned host) {end_to_end_ms:.4f} ms")
 
     # ---------------------------------------------------------------- hardware-counter runs
     if args.only == "counters":
@@ -241,9 +268,12 @@ def main():
 
         batched_fa()
         plain_fa()
-        tb = time_calls(batched_fa, 10, sync)
-        tp = time_calls(plain_fa, 10, sync)
-        # the plain form is 16 C-ABI calls per step: its time depends on the host as much as on the GPU
+        # wall clock with a final synchronisation, best of three runs of 10 steps: HIP event pairs
+        # around the plain form (16 calls that each upload a new hologram's tables) were seen to
+        # report many times the time the work took, and single runs of it vary with transient
+        # stalls of the host runtime, so both forms are timed the same way from the host
+        tb = min(time_wall(batched_fa, 10, sync) for _ in range(3))
+        tp = min(time_wall(plain_fa, 10, sync) for _ in range(3))
         sync()
         h0 = time.perf_counter()
         for _ in range(10):
@@ -375,10 +405,27 @@ def main():
         t0 = time.perf_counter()
         oracle.solve("gsw", p.slm, p.xyz, p.theta0, Ks)
         dt = time.perf_counter() - t0
-        cpu = {"value": N * M * Ks / dt, "unit": "pixel-trap updates/s", "cores": oracle.get_threads(),
+        # the same oracle on one thread, on a shorter sample (2 iterations, 6 passes)
+        threads = oracle.get_threads()
+        K1 = 2
+        oracle.set_threads(1)
+        t1 = time.perf_counter()
+        oracle.solve("gsw", p.slm, p.xyz, p.theta0, K1)
+        dt1 = time.perf_counter() - t1
+        oracle.set_threads(threads)
+        model = None
+        try:
+            with open("/proc/cpuinfo") as f:
+                model = next((ln.split(":", 1)[1].strip() for ln in f if ln.startswith("model name")), None)
+        except OSError:
+            pass
+        cpu = {"value": N * M * Ks / dt, "unit": "pixel-trap updates/s", "cores": threads,
                "kind": "oracle", "sample": f"FP64 oracle GSW on the same 512^2 x 100 problem, {Ks} iterations "
-                                           f"({2 * Ks + 2} passes), {dt:.2f} s"}
-        log(f"[bench] cpu oracle {dt:.2f} s for {Ks} iterations on {cpu['cores']} threads")
+                                           f"({2 * Ks + 2} passes), {dt:.2f} s",
+               "one_thread": {"value": N * M * K1 / dt1, "sample": f"{K1} iterations ({2 * K1 + 2} passes), {dt1:.2f} s"},
+               "host_cpu": model, "host_logical_cpus": os.cpu_count()}
+        log(f"[bench] cpu oracle {dt:.2f} s for {Ks} iterations on {threads} threads; {dt1:.2f} s for {K1} "
+            f"iterations on 1 thread ({model})")
 
     if ms is None:
         print(json.dumps({"section": args.only, **out, "roofline": roof}))
@@ -393,6 +440,10 @@ def main():
                    "algorithm": "GSW", "variant": "on-the-fly Delta", "parallelism": "single GPU",
                    "launch_shape": "library default"},
         "holograms_per_s": 1e3 / ms,
+        "terms_per_s": 2 * N * M * (K + 1) / (ms * 1e-3),
+        "end_to_end_ms": None if end_to_end_ms is None else round(end_to_end_ms, 4),
+        "paper_context": {"updates_per_s": 1.34e9, "note": "the paper's GSW rate (0.44 ms per trap per iteration "
+                          "at 768^2 on a GeForce GTX 260): other hardware and grid, not a target"},
         "roofline": roof, "cpu_baseline": cpu, "tuning": tuning, **out,
     }
     print(json.dumps(line))

@@ -46,7 +46,8 @@ struct DevBuf {
 };
 
 struct Staging {
-  void* host = nullptr;
+  void* host = nullptr;  // pinned host memory
+  void* dev = nullptr;   // the same memory as the device addresses it
   size_t cap = 0;
   hipEvent_t ev = nullptr;
   bool pending = false;
@@ -112,9 +113,14 @@ int ensure(hot_ctx* c, DevBuf& b, size_t bytes) {
 }
 
 // Asynchronous host-to-device copy through a ring of pinned staging buffers, so the
-// caller's host arrays may be reused as soon as the call returns.
+// caller's host arrays may be reused as soon as the call returns.  The copy is a kernel on the
+// context's stream that reads the pinned buffer through its device mapping (the runtime's own
+// copy of a few hundred bytes was measured to stall the stream for ~0.5 ms after some launch
+// sequences); a slot is reused only after the event behind its copy has completed.  Sizes are
+// multiples of 16 bytes (the tables are arrays of 16- and 32-byte records).
 int upload(hot_ctx* c, void* dst, const void* src, size_t bytes) {
   if (bytes == 0) return HOT_OK;
+  if (bytes % 16 != 0) return fail(HOT_EINVAL, "internal: upload of %zu bytes is not a multiple of 16", bytes);
   Staging& s = c->ring[c->ring_pos];
   c->ring_pos = (c->ring_pos + 1) % kRing;
   if (s.pending) {
@@ -124,6 +130,7 @@ int upload(hot_ctx* c, void* dst, const void* src, size_t bytes) {
   if (s.cap < bytes) {
     if (s.host) HIP_TRY(hipHostFree(s.host));
     s.host = nullptr;
+    s.dev = nullptr;
     s.cap = 0;
     size_t want = std::max<size_t>(bytes, 4096);
     hipError_t e = hipHostMalloc(&s.host, want, hipHostMallocDefault);
@@ -131,10 +138,18 @@ int upload(hot_ctx* c, void* dst, const void* src, size_t bytes) {
       (void)hipGetLastError();
       return fail(HOT_ENOMEM, "pinned host allocation of %zu bytes failed", want);
     }
+    e = hipHostGetDevicePointer(&s.dev, s.host, 0);
+    if (e != hipSuccess || !s.dev) {
+      (void)hipGetLastError();
+      (void)hipHostFree(s.host);
+      s.host = nullptr;
+      s.dev = nullptr;
+      return fail(HOT_EDEVICE, "pinned staging buffer has no device mapping");
+    }
     s.cap = want;
   }
   memcpy(s.host, src, bytes);
-  HIP_TRY(hipMemcpyAsync(dst, s.host, bytes, hipMemcpyHostToDevice, c->stream));
+  HIP_TRY(launch_copy16(c->stream, s.dev, dst, bytes / 16));
   HIP_TRY(hipEventRecord(s.ev, c->stream));
   s.pending = true;
   return HOT_OK;

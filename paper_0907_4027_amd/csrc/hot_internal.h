@@ -168,6 +168,8 @@ hipError_t launch_encode_u8(hipStream_t s, const float* phase, uint8_t* frame, i
 
 // Small helpers.
 hipError_t launch_fill_u32(hipStream_t s, unsigned* p, unsigned v, int n);
+// dst <- src, n16 16-byte words (src: device memory or the device mapping of pinned host memory).
+hipError_t launch_copy16(hipStream_t s, const void* src, void* dst, size_t n16);
 hipError_t launch_export_state(hipStream_t s, const TrapState* st, int t, float* w_out, float* theta_out);
 hipError_t launch_import_w(hipStream_t s, const float* w0, TrapState* st, int t);
 

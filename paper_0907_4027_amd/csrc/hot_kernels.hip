@@ -1213,6 +1213,12 @@ __global__ void __launch_bounds__(256) k_encode_u8(const float* __restrict__ pha
   }
 }
 
+// dst[i] = src[i] for n 16-byte words; src may be pinned host memory (read through its device
+// mapping), dst device memory.
+__global__ void __launch_bounds__(256) k_copy16(const uint4* __restrict__ src, uint4* __restrict__ dst, size_t n) {
+  for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (size_t)gridDim.x * 256) dst[i] = src[i];
+}
+
 __global__ void k_fill_u32(unsigned* p, unsigned v, int n) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) p[i] = v;
@@ -1439,6 +1445,13 @@ hipError_t launch_sep(hipStream_t s, const SepArgs& a) {
 hipError_t launch_encode_u8(hipStream_t s, const float* phase, uint8_t* frame, int64_t n) {
   const int64_t blocks = std::min<int64_t>((n + 255) / 256, 4096);
   hipLaunchKernelGGL(k_encode_u8, dim3((unsigned)std::max<int64_t>(blocks, 1)), dim3(256), 0, s, phase, frame, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_copy16(hipStream_t s, const void* src, void* dst, size_t n16) {
+  if (n16 == 0) return hipSuccess;
+  const size_t blocks = std::min<size_t>((n16 + 255) / 256, 1024);
+  hipLaunchKernelGGL(k_copy16, dim3((unsigned)blocks), dim3(256), 0, s, (const uint4*)src, (uint4*)dst, n16);
   return hipGetLastError();
 }
 
