@@ -292,7 +292,7 @@ int prepare(hot_ctx* c, const hot_slm* slm, int B, const int32_t* counts, const 
   P.fgf = row_segments(slm->nx, slm->ny, c->tune_seg > 0 ? c->tune_seg : kSegMax);
   P.nblk_stored = stored_nblk(P.n);
   {
-    // separable: the widest block (most waves sharing one update and one partial per trap) that
+    // separable: the widest block (most waves sharing one update and one sum per trap) that
     // still gives every compute unit a block
     const int rows = (slm->ny + 15) / 16;
     int w = c->tune_sepw;
@@ -699,7 +699,7 @@ int hot_destroy(hot_ctx* c) {
   (void)hipSetDevice(c->device);
   (void)hipStreamSynchronize(c->stream);
   for (auto& g : c->graphs) (void)hipGraphExecDestroy(g.exec);
-  for (DevBuf* b : {&c->coef, &c->st, &c->hd, &c->partial, &c->stats, &c->flag, &c->amat, &c->efield})
+  for (DevBuf* b : {&c->coef, &c->st, &c->hd, &c->partial, &c->stats, &c->flag, &c->amat, &c->efield, &c->acc})
     if (b->p) (void)hipFree(b->p);
   for (auto& s : c->ring) {
     if (s.pending && s.ev) (void)hipEventSynchronize(s.ev);
