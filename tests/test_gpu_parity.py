@@ -354,6 +354,24 @@ def test_max_traps(ctx, algo):
     assert_V(to_np(g.V), o["V"])
 
 
+def test_contexts_release_device_memory(hot):
+    """Contexts free every device buffer they allocate: 30 create / solve / destroy cycles with
+    2048 traps (each context holding about 1 MB of trap tables, sums and partials) leave the free
+    device memory where it was."""
+    p = W.Problem(W.Slm(64, 64), W.square_grid(46, 3e-6)[:2048], W.random_phases(460, 2048), 2)
+    with hot.Context(0) as c:  # allocator warm-up for the output tensors
+        c.hot_gsw(p.slm, p.xyz, p.theta0, p.iters)
+    torch.cuda.synchronize()
+    free0 = torch.cuda.mem_get_info(0)[0]
+    for _ in range(30):
+        with hot.Context(0) as c:
+            c.hot_gsw(p.slm, p.xyz, p.theta0, p.iters)
+            c.hot_forward_V(p.slm, [2048], p.xyz, torch.zeros(1, 64, 64, device="cuda"))
+    torch.cuda.synchronize()
+    free1 = torch.cuda.mem_get_info(0)[0]
+    assert free0 - free1 < 8 << 20, f"{(free0 - free1) / 2**20:.1f} MiB of device memory not returned"
+
+
 def test_bad_arguments_on_gpu(hot, ctx):
     p = W.random_problem(390, 32, 32, 4)
     with pytest.raises(hot.HotError) as e:
