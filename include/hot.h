@@ -104,7 +104,7 @@ int hot_set_variant(hot_ctx* ctx, int variant);
  * beyond FP32 summation order. */
 enum hot_tuning_key {
   HOT_TUNE_PIXELS_PER_LANE = 1, /* pixel pass: pixels per lane, 1, 2 or 4 */
-  HOT_TUNE_TRAPS_PER_LANE = 2,  /* trap pass: traps each lane accumulates, 1..8 */
+  HOT_TUNE_TRAPS_PER_LANE = 2,  /* trap pass: traps each lane accumulates: 1..6 or 8 */
   HOT_TUNE_SEGMENT = 3,         /* trap pass: pixels of a row per block, 64..1024 */
   HOT_TUNE_SLICES = 4,          /* trap pass: at most this many pixel slices per wave, 1..16 */
   HOT_TUNE_GRAPHS = 5,          /* 1 (default): replay a captured hipGraph of a solve's launch

@@ -312,21 +312,20 @@ __device__ __forceinline__ void pad_records(float4* rec, int M) {
 //   t = phi - a_m U - g_m U^2                2 VALU
 //   sin t, cos t                             2 transcendental
 //   acc += mask (cos t, sin t)              2 VALU
-// The row-constant part of Eq. 2, C_m = g V^2 + b V, is taken out of the sum: each lane's
-// accumulator is turned by e^{-i 2pi C_m} once, after its pixels.  The S slice partials of
-// each trap are then summed in slice order through LDS `red` and handed to store(m, sum).
-// The coefficients one trap-pass lane needs for the traps it owns in one chunk: -a, -g and the
-// row constant C_m = g V^2 + b V (revolutions).  Traps past M get zeros (their sums are unused).
-template <int TPL>
-struct LaneCoef {
-  float na[TPL], ng[TPL], cc[TPL];
-};
+// The S slice partials of each trap are then summed in slice order through LDS `red`.  The
+// row-constant part of Eq. 2, C_m = g V^2 + b V, is left out of the pixel sums: the sum of each
+// trap over a row is turned by e^{-i 2pi C_m} once, by the thread that sums its slices, and
+// handed to store(m, sum).
+// The coefficients one trap-pass lane needs for the traps it owns in one chunk: -a and -g.
 // Slots past M take trap M - 1's coefficients (always a valid read, and the arguments stay in
 // the sin/cos domain); their sums are never written out.  The loads are unconditional so that
 // the compiler need not wait for them where a conditional default would be merged in.
 template <int TPL>
-__device__ __forceinline__ LaneCoef<TPL> load_lane_coef(const TrapCoef* __restrict__ cf, int M, int G, int k0,
-                                                        float Vr, float V2) {
+struct LaneCoef {
+  float na[TPL], ng[TPL];
+};
+template <int TPL>
+__device__ __forceinline__ LaneCoef<TPL> load_lane_coef(const TrapCoef* __restrict__ cf, int M, int G, int k0) {
   const int lane = threadIdx.x & 63;
   const int tl = lane - lane / G * G;
   LaneCoef<TPL> lc;
@@ -335,20 +334,36 @@ __device__ __forceinline__ LaneCoef<TPL> load_lane_coef(const TrapCoef* __restri
     const TrapCoef c = cf[min(k0 + tl + k * G, M - 1)];
     lc.na[k] = -c.a;
     lc.ng[k] = -c.g;
-    lc.cc[k] = __builtin_fmaf(c.g, V2, c.b * Vr);
   }
   return lc;
 }
 
-// `first` holds the lane's coefficients of the first chunk (k0 = 0), loaded by the caller before
-// its own global stores, so that waiting for them does not wait for those stores too.
-// With ROWS = 2 the block is two halves of W waves, each passing over its own row (px, len, Vr
-// of the calling thread's half); the slice partials of both rows are summed together, so
-// store(m, sum) gets the block's sum over both rows.
+// The same coefficients from the staged pixel-pass records {a, g, ., w} of the first chunk (k0 = 0).
+template <int TPL>
+__device__ __forceinline__ LaneCoef<TPL> lane_coef_from_records(const float4* rec, int M, int G) {
+  const int lane = threadIdx.x & 63;
+  const int tl = lane - lane / G * G;
+  LaneCoef<TPL> lc;
+#pragma unroll
+  for (int k = 0; k < TPL; ++k) {
+    const float4 r = rec[min(tl + k * G, M - 1)];
+    lc.na[k] = -r.x;
+    lc.ng[k] = -r.y;
+  }
+  return lc;
+}
+
+// `first` holds the lane's coefficients of the first chunk (k0 = 0) and `cfirst` trap
+// min(threadIdx.x, M - 1)'s record, both read by the caller before its own global stores, so
+// that waiting for them does not wait for those stores too.
+// With ROWS = 2 the block is two halves of W waves, each passing over its own row (px and len of
+// the calling thread's half); Vb is the row coordinate V of the first half, Vb + 2 that of the
+// second.  store(m, sum) gets the block's sum over its rows.
 template <int W, int TPL, bool FRACT, int ROWS, class Store>
-__device__ __forceinline__ void trap_pass_block(const TrapCoef* __restrict__ cf, int M, int G, int A, float Vr,
-                                                float V2, const float4* px, int len, float2* red, Store store,
-                                                const LaneCoef<TPL>& first) {
+__device__ __forceinline__ void trap_pass_block(const TrapCoef* __restrict__ cf, int M, int G, int A, float Vb,
+                                                const float4* px, int len, float2* red, Store store,
+                                                const LaneCoef<TPL>& first, const TrapCoef& cfirst) {
+  constexpr int NB = ROWS * W * 64;
   const int half = (int)threadIdx.x / (W * 64);
   const int wave = ((int)threadIdx.x >> 6) - half * W, lane = threadIdx.x & 63;
   const int s = lane / G, tl = lane - s * G;
@@ -359,13 +374,14 @@ __device__ __forceinline__ void trap_pass_block(const TrapCoef* __restrict__ cf,
   const float4* mine = px + sidx * slen;
   const int nslot = G * TPL;
   for (int k0 = 0; k0 < M; k0 += nslot) {
-    const LaneCoef<TPL> lc = k0 == 0 ? first : load_lane_coef<TPL>(cf, M, G, k0, Vr, V2);
-    float na[TPL], ng[TPL], cc[TPL], accr[TPL], acci[TPL];
+    const LaneCoef<TPL> lc = k0 == 0 ? first : load_lane_coef<TPL>(cf, M, G, k0);
+    // record of the trap this thread sums first after the pixels (read now, used after them)
+    const TrapCoef cm = k0 == 0 ? cfirst : cf[min(k0 + (int)threadIdx.x, M - 1)];
+    float na[TPL], ng[TPL], accr[TPL], acci[TPL];
 #pragma unroll
     for (int k = 0; k < TPL; ++k) {
       na[k] = lc.na[k];
       ng[k] = lc.ng[k];
-      cc[k] = to_period<FRACT>(lc.cc[k]);
       accr[k] = 0.0f;
       acci[k] = 0.0f;
     }
@@ -413,27 +429,53 @@ __device__ __forceinline__ void trap_pass_block(const TrapCoef* __restrict__ cf,
         terms(pc, pd);
       }
     }
-#pragma unroll
-    for (int k = 0; k < TPL; ++k) {  // acc *= e^{-i 2pi C}
-      const float cs = __builtin_amdgcn_cosf(cc[k]), sn = __builtin_amdgcn_sinf(cc[k]);
-      const float re = __builtin_fmaf(accr[k], cs, acci[k] * sn);
-      acci[k] = __builtin_fmaf(acci[k], cs, -accr[k] * sn);
-      accr[k] = re;
-    }
     __syncthreads();  // red[] is free: earlier readers (previous chunk, or the pixel pass) are done
     if (active) {
 #pragma unroll
       for (int k = 0; k < TPL; ++k) red[(half * S + sidx) * nslot + tl + k * G] = make_float2(accr[k], acci[k]);
     }
     __syncthreads();
-    for (int i = threadIdx.x; i < nslot; i += ROWS * W * 64) {
+    for (int i = threadIdx.x; i < nslot; i += NB) {
       const int m = k0 + i;
       if (m < M) {
+        const TrapCoef c = i == (int)threadIdx.x ? cm : cf[m];
         float2 acc = make_float2(0.0f, 0.0f);
-        for (int s2 = 0; s2 < ROWS * S; ++s2) {
-          const float2 v = red[s2 * nslot + i];
-          acc.x += v.x;
-          acc.y += v.y;
+#pragma unroll
+        for (int h = 0; h < ROWS; ++h) {
+          // the slices in order; the reads go out in groups so that their latencies overlap
+          const float2* rp = red + h * S * nslot + i;
+          float sr = 0.0f, si = 0.0f;
+          int s2 = 0;
+          for (; s2 + 8 <= S; s2 += 8) {
+            float2 v[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) v[u] = rp[(s2 + u) * nslot];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+              sr += v[u].x;
+              si += v[u].y;
+            }
+          }
+          if (s2 + 4 <= S) {
+            float2 v[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) v[u] = rp[(s2 + u) * nslot];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+              sr += v[u].x;
+              si += v[u].y;
+            }
+            s2 += 4;
+          }
+          for (; s2 < S; ++s2) {
+            sr += rp[s2 * nslot].x;
+            si += rp[s2 * nslot].y;
+          }
+          const float vr = Vb + 2.0f * (float)h;
+          const float t = to_period<FRACT>(__builtin_fmaf(c.g, vr * vr, c.b * vr));
+          const float cs = __builtin_amdgcn_cosf(t), sn = __builtin_amdgcn_sinf(t);
+          acc.x += __builtin_fmaf(sr, cs, si * sn);  // (sr + i si) e^{-i 2pi t}
+          acc.y += __builtin_fmaf(si, cs, -sr * sn);
         }
         store(m, acc);
       }
@@ -481,8 +523,6 @@ k_iter(HoloDesc one, const TrapCoef* __restrict__ coef, const TrapState* __restr
   const HoloDesc d = one.m > 0 ? one : hd[b];
   const int M = d.m, off = d.off, G = d.g, A = d.a;
   const TrapCoef* __restrict__ cf = coef + off;
-  const float Vr = (float)(2 * r - (ny - 1));
-  const float V2 = Vr * Vr;
   float4* rec_all = reinterpret_cast<float4*>(ubuf);
   float4* px = pxs + half * PXN;
   const bool lead = sg == 0 && blockIdx.y == 0;
@@ -494,7 +534,6 @@ k_iter(HoloDesc one, const TrapCoef* __restrict__ coef, const TrapState* __restr
   const TrapCoef c_first = cf[tm];
   const TrapState s_first = st_in[off + tm];
   const float2 v_first = vacc(tm);
-  const LaneCoef<TPL> lane_first = load_lane_coef<TPL>(cf, M, G, 0, Vr, V2);
   if (lead) {
     for (int i = threadIdx.x; i < kAccRegions * M; i += NB) {
       const int g = i / M;
@@ -536,6 +575,8 @@ k_iter(HoloDesc one, const TrapCoef* __restrict__ coef, const TrapState* __restr
     si[q] = 0.0f;
   }
   pixel_terms<Q, FRACT>(rec_all + half * RECN, M, U, U2, sr, si);
+  // the trap pass's first-chunk coefficients, from the records while they are still in LDS
+  const LaneCoef<TPL> lane_first = lane_coef_from_records<TPL>(rec_all, M, G);
   float* __restrict__ prow = phase + (size_t)b * nx * ny + (size_t)r * nx + cbeg;
 #pragma unroll
   for (int q = 0; q < Q; ++q) {
@@ -558,7 +599,8 @@ k_iter(HoloDesc one, const TrapCoef* __restrict__ coef, const TrapState* __restr
     __hip_atomic_fetch_add(p + 1, (unsigned long long)(long long)(v.y * scale), __ATOMIC_RELAXED,
                            __HIP_MEMORY_SCOPE_AGENT);
   };
-  trap_pass_block<W, TPL, FRACT, ROWS>(cf, M, G, A, Vr, V2, px, len, ubuf, add_sum, lane_first);
+  trap_pass_block<W, TPL, FRACT, ROWS>(cf, M, G, A, (float)(2 * (int)(blockIdx.y * ROWS) - (ny - 1)), px, len,
+                                       ubuf, add_sum, lane_first, c_first);
 }
 
 // ------------------------------------------------------------------ stand-alone passes
@@ -634,7 +676,8 @@ k_forward(const TrapCoef* __restrict__ coef, const HoloDesc* __restrict__ hd, co
   const int padded = S * ((len + S - 1) / S) + 4;  // zeros past the last slice for the read-ahead
   const float* __restrict__ ph = phase + (size_t)b * nx * ny + (size_t)r * nx + cbeg;
   const float Vr = (float)(2 * r - (ny - 1));
-  const LaneCoef<TPL> lane_first = load_lane_coef<TPL>(coef + off, M, G, 0, Vr, Vr * Vr);
+  const LaneCoef<TPL> lane_first = load_lane_coef<TPL>(coef + off, M, G, 0);
+  const TrapCoef c_first = coef[off + min((int)threadIdx.x, M - 1)];
   for (int i = threadIdx.x; i < padded; i += kBlock) {
     if (i < len) {
       const float U = (float)(2 * (cbeg + i) - (nx - 1));
@@ -646,8 +689,8 @@ k_forward(const TrapCoef* __restrict__ coef, const HoloDesc* __restrict__ hd, co
   __syncthreads();
   const int nblk = ny * nseg;
   float2* __restrict__ out = partial + (size_t)off * nblk + r * nseg + sg;
-  trap_pass_block<W, TPL, FRACT, 1>(coef + off, M, G, A, Vr, Vr * Vr, px, len, red,
-                                 [&](int m, float2 v) { out[(size_t)m * nblk] = v; }, lane_first);
+  trap_pass_block<W, TPL, FRACT, 1>(coef + off, M, G, A, Vr, px, len, red,
+                                    [&](int m, float2 v) { out[(size_t)m * nblk] = v; }, lane_first, c_first);
 }
 
 // ------------------------------------------------------------------ reduce, update, finalize
