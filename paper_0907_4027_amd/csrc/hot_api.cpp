@@ -266,8 +266,10 @@ int prepare(hot_ctx* c, const hot_slm* slm, int B, const int32_t* counts, const 
   {
     int lg = 0;
     while ((1LL << lg) < (long long)P.n) ++lg;
-    P.acc_scale = (float)std::ldexp(1.0, 61 - lg);
-    P.acc_unscale = (float)(std::ldexp(1.0, lg - 61) / (double)P.n);
+    // fixed-point trap sums (re and im packed into one 64-bit word): any sum of at most N
+    // unit-modulus terms stays within 2^30 units of 2^-(30 - lg)
+    P.acc_scale = (float)std::ldexp(1.0, 30 - lg);
+    P.acc_unscale = (float)(std::ldexp(1.0, lg - 30) / (double)P.n);
   }
   P.T = 0;
   P.mmax = 0;
@@ -463,9 +465,9 @@ SepArgs sep_args(hot_ctx* c, const Plan& P, int mode, float* phase, int K) {
 
 // Buffer i (0..2) of the iteration kernels' rotating fixed-point sums.
 unsigned long long* acc_buf(hot_ctx* c, const Plan& P, int i) {
-  return (unsigned long long*)c->acc.p + (size_t)i * 2 * kAccRegions * P.T;
+  return (unsigned long long*)c->acc.p + (size_t)i * kAccRegions * P.T;
 }
-int ensure_acc(hot_ctx* c, const Plan& P) { return ensure(c, c->acc, 3 * sizeof(uint64_t) * 2 * kAccRegions * P.T); }
+int ensure_acc(hot_ctx* c, const Plan& P) { return ensure(c, c->acc, 3 * sizeof(uint64_t) * kAccRegions * P.T); }
 
 IterArgs iter_args(hot_ctx* c, const Plan& P, float* phase, int K) {
   IterArgs a;
@@ -520,7 +522,7 @@ int solve(hot_ctx* c, const hot_slm* slm, int B, const int32_t* counts, const do
     if (separable) {
       // one launch per iteration, with the same rotation of fixed-point sums as the direct path
       SepArgs a = sep_args(c, P, 0, phase, K);
-      e = launch_fill_u32(s, (unsigned*)acc_buf(c, P, 1), 0u, 4 * kAccRegions * P.T);
+      e = launch_fill_u32(s, (unsigned*)acc_buf(c, P, 1), 0u, 2 * kAccRegions * P.T);
       for (int k = 0; k <= K && e == hipSuccess; ++k) {
         a.upd = k == 0 ? 0 : upd;
         a.st_in = k == 0 ? st[0] : st[(k - 1) & 1];
@@ -536,7 +538,7 @@ int solve(hot_ctx* c, const hot_slm* slm, int B, const int32_t* counts, const do
       // one launch per iteration: launch k reads buffer k % 3, adds into (k + 1) % 3 (buffer 1 is
       // cleared first, the others by the launches) and clears (k + 2) % 3
       IterArgs a = iter_args(c, P, phase, K);
-      e = launch_fill_u32(s, (unsigned*)acc_buf(c, P, 1), 0u, 4 * kAccRegions * P.T);
+      e = launch_fill_u32(s, (unsigned*)acc_buf(c, P, 1), 0u, 2 * kAccRegions * P.T);
       for (int k = 0; k <= K && e == hipSuccess; ++k) {
         a.upd = k == 0 ? 0 : upd;
         a.st_in = k == 0 ? st[0] : st[(k - 1) & 1];
@@ -942,7 +944,7 @@ int hot_time_passes(hot_ctx* c, const hot_slm* slm, int32_t M, const double* xyz
   // a fused path's buffer 0: sums of the theta0 mask (a pass without update)
   auto prime = [&]() -> hipError_t {
     if (stored) return hipSuccess;
-    hipError_t e = launch_fill_u32(c->stream, (unsigned*)acc_buf(c, P, 0), 0u, 4 * kAccRegions * P.T);
+    hipError_t e = launch_fill_u32(c->stream, (unsigned*)acc_buf(c, P, 0), 0u, 2 * kAccRegions * P.T);
     if (e != hipSuccess) return e;
     if (separable) {
       SepArgs p0 = sa;

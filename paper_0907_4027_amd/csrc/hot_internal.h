@@ -76,7 +76,7 @@ struct IterArgs {
   unsigned long long* acc_out = nullptr;       // sums of this launch's mask (added to; cleared beforehand)
   unsigned long long* acc_zero = nullptr;      // cleared here for the launch after next
   int T = 0;                                   // traps of all holograms of the launch
-  float acc_scale = 0.0f, acc_unscale = 0.0f;  // 2^s, and 2^-s / N
+  float acc_scale = 0.0f, acc_unscale = 0.0f;  // 2^s, and 2^-s / N (s = 30 - ceil(log2 N))
   float* stats = nullptr;
   int kstat = 0, stat_stride = 1;
   int upd = 0;                   // 0 none, 1 GS, 2 GSW

@@ -146,21 +146,28 @@ struct VArray {
   int off;
   __device__ float2 operator()(int k) const { return make_float2(V[2 * (off + k)], V[2 * (off + k) + 1]); }
 };
-// ... or from the fixed-point sums of the direct path: kAccRegions regions of T (re, im)
-// pairs of 64-bit integers (two's complement), V = (sum over regions) * unscale.
+// ... or from the fixed-point sums of the fused kernels: kAccRegions regions of T 64-bit words.
+// A block adds its sum (re, im) of a trap as one word, pack_sum: re and im are rounded to
+// integers in units of 1/scale, and the word is the 64-bit two's-complement value
+// re + 2^32 im.  Words add like integers, so a sum of words is R + 2^32 I with R, I the sums of
+// the parts; as long as |R| < 2^31 (the host picks scale so that any sum of N unit-modulus terms
+// stays within 2^30), R is the low 32 bits read as signed, and I the high 32 bits plus one if R
+// is negative.  V = (R, I) * unscale.
+__device__ __forceinline__ unsigned long long pack_sum(float2 v, float scale) {
+  const int re = (int)__builtin_rintf(v.x * scale), im = (int)__builtin_rintf(v.y * scale);
+  return (unsigned long long)(long long)re + ((unsigned long long)(unsigned)im << 32);
+}
 struct VAcc {
-  const ulonglong2* __restrict__ acc;
+  const unsigned long long* __restrict__ acc;
   int T, off;
   float unscale;
   __device__ float2 operator()(int k) const {
-    unsigned long long re = 0, im = 0;
+    unsigned long long w = 0;
 #pragma unroll
-    for (int r = 0; r < kAccRegions; ++r) {
-      const ulonglong2 v = acc[(size_t)r * T + off + k];
-      re += v.x;
-      im += v.y;
-    }
-    return make_float2((float)(long long)re * unscale, (float)(long long)im * unscale);
+    for (int r = 0; r < kAccRegions; ++r) w += acc[(size_t)r * T + off + k];
+    const int re = (int)(unsigned)w;
+    const int im = (int)((unsigned)(w >> 32) - (unsigned)(re >> 31));
+    return make_float2((float)re * unscale, (float)im * unscale);
   }
 };
 
@@ -492,9 +499,9 @@ __device__ __forceinline__ void trap_pass_block(const TrapCoef* __restrict__ cf,
 //   recomputed by every block; block (0, 0, b) also writes the new state to st_out and the
 //   figures of merit of that V to stats[b][kstat].
 //   V is not a separate array: the previous launch added each block's trap sums to acc_in as
-//   64-bit fixed point (value * scale, truncated), one region per XCD (the XCC_ID of the adding
-//   wave) so that the atomics of different XCDs do not contend; integer sums do not depend on
-//   the order of the adds, so the result is deterministic.  This launch adds its own sums to
+//   fixed-point words (pack_sum: re and im in one 64-bit atomic add), one region per XCD (the
+//   XCC_ID of the adding wave) so that the atomics of different XCDs do not contend; integer
+//   sums do not depend on the order of the adds, so the result is deterministic.  This launch adds its own sums to
 //   acc_out, and block (0, 0, b) clears hologram b's part of acc_zero for the launch after next.
 //   acc_in is read even when upd == 0 (it must be a valid buffer; the values are then unused).
 //   one.m > 0: a single hologram whose descriptor comes by value, so no load waits for it.
@@ -504,8 +511,9 @@ __device__ __forceinline__ void trap_pass_block(const TrapCoef* __restrict__ cf,
 template <int NT, int Q, int TPL, bool FRACT, int ROWS>
 __global__ void __launch_bounds__(NT * ROWS)
 k_iter(HoloDesc one, const TrapCoef* __restrict__ coef, const TrapState* __restrict__ st_in,
-       const ulonglong2* __restrict__ acc_in, const HoloDesc* __restrict__ hd, TrapState* __restrict__ st_out,
-       ulonglong2* __restrict__ acc_out, ulonglong2* __restrict__ acc_zero, int T, float scale, float unscale,
+       const unsigned long long* __restrict__ acc_in, const HoloDesc* __restrict__ hd,
+       TrapState* __restrict__ st_out, unsigned long long* __restrict__ acc_out,
+       unsigned long long* __restrict__ acc_zero, int T, float scale, float unscale,
        float* __restrict__ stats, int kstat, int stat_stride, int upd, int* __restrict__ flag, int nx, int ny,
        int seg_w, float* __restrict__ phase) {
   constexpr int W = NT / 64;        // waves per half
@@ -537,7 +545,7 @@ k_iter(HoloDesc one, const TrapCoef* __restrict__ coef, const TrapState* __restr
   if (lead) {
     for (int i = threadIdx.x; i < kAccRegions * M; i += NB) {
       const int g = i / M;
-      acc_zero[(size_t)g * T + off + (i - g * M)] = make_ulonglong2(0ull, 0ull);
+      acc_zero[(size_t)g * T + off + (i - g * M)] = 0ull;
     }
   }
   auto coef_of = [&](int m) { return m == (int)threadIdx.x ? c_first : cf[m]; };
@@ -591,13 +599,9 @@ k_iter(HoloDesc one, const TrapCoef* __restrict__ coef, const TrapState* __restr
   }
   for (int i = NT * Q + tid; i < PXN; i += NT) px[i] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
   __syncthreads();
-  ulonglong2* __restrict__ mine = acc_out + (size_t)(xcc_id() & (kAccRegions - 1)) * T + off;
+  unsigned long long* __restrict__ mine = acc_out + (size_t)(xcc_id() & (kAccRegions - 1)) * T + off;
   auto add_sum = [&](int m, float2 v) {
-    unsigned long long* p = reinterpret_cast<unsigned long long*>(mine + m);
-    __hip_atomic_fetch_add(p, (unsigned long long)(long long)(v.x * scale), __ATOMIC_RELAXED,
-                           __HIP_MEMORY_SCOPE_AGENT);
-    __hip_atomic_fetch_add(p + 1, (unsigned long long)(long long)(v.y * scale), __ATOMIC_RELAXED,
-                           __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_fetch_add(mine + m, pack_sum(v, scale), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   };
   trap_pass_block<W, TPL, FRACT, ROWS>(cf, M, G, A, (float)(2 * (int)(blockIdx.y * ROWS) - (ny - 1)), px, len,
                                        ubuf, add_sum, lane_first, c_first);
@@ -721,7 +725,7 @@ k_reduce(const float2* __restrict__ partial, const HoloDesc* __restrict__ hd, in
 
 // V of all T traps from the fixed-point region sums of the direct path (one thread per trap).
 __global__ void __launch_bounds__(256)
-k_collect(const ulonglong2* __restrict__ acc, int T, float unscale, float* __restrict__ V) {
+k_collect(const unsigned long long* __restrict__ acc, int T, float unscale, float* __restrict__ V) {
   const int t = blockIdx.x * 256 + threadIdx.x;
   if (t >= T) return;
   const float2 v = VAcc{acc, T, 0, unscale}(t);
@@ -732,7 +736,7 @@ k_collect(const ulonglong2* __restrict__ acc, int T, float unscale, float* __res
 // End of a solve on the fixed-point path, one block per hologram: V of its traps from the sums
 // (written to V) and their figures of merit into stats[b][kstat].
 __global__ void __launch_bounds__(256)
-k_finish(const ulonglong2* __restrict__ acc, int T, float unscale, const HoloDesc* __restrict__ hd,
+k_finish(const unsigned long long* __restrict__ acc, int T, float unscale, const HoloDesc* __restrict__ hd,
          const TrapState* __restrict__ st, float* __restrict__ V, float* __restrict__ stats, int kstat,
          int stat_stride) {
   __shared__ float sh[8 * 4];
@@ -1000,8 +1004,8 @@ k_sep(const TrapCoef* __restrict__ coef, const HoloDesc* __restrict__ hd, const 
       TrapState* __restrict__ st_out, const float* __restrict__ vin, float* __restrict__ stats, int kstat,
       int stat_stride, int upd, int* __restrict__ flag, int nx, int ny, float inv_n, int sc,
       float* __restrict__ phase, float* __restrict__ grad, float2* __restrict__ partial,
-      const ulonglong2* __restrict__ acc_in, ulonglong2* __restrict__ acc_out, ulonglong2* __restrict__ acc_zero,
-      int T, float scale, float unscale) {
+      const unsigned long long* __restrict__ acc_in, unsigned long long* __restrict__ acc_out,
+      unsigned long long* __restrict__ acc_zero, int T, float scale, float unscale) {
   constexpr int NT = W * 64, CW = 16 * W;
   constexpr bool kPixel = MODE != 1, kTrap = MODE <= 1;
   extern __shared__ float4 lds4[];
@@ -1087,7 +1091,7 @@ k_sep(const TrapCoef* __restrict__ coef, const HoloDesc* __restrict__ hd, const 
   if (MODE == 0 && lead) {
     for (int i = threadIdx.x; i < kAccRegions * M; i += NT) {
       const int gi = i / M;
-      acc_zero[(size_t)gi * T + off + (i - gi * M)] = make_ulonglong2(0ull, 0ull);
+      acc_zero[(size_t)gi * T + off + (i - gi * M)] = 0ull;
     }
   }
   for (int m = NT + (int)threadIdx.x; m < Mp; m += NT) {
@@ -1230,12 +1234,8 @@ k_sep(const TrapCoef* __restrict__ coef, const HoloDesc* __restrict__ hd, const 
           acc.y += red[w * sc + m].y;
         }
         if constexpr (MODE == 0) {
-          unsigned long long* p =
-              reinterpret_cast<unsigned long long*>(acc_out + (size_t)(xcc_id() & (kAccRegions - 1)) * T + off + k0 + m);
-          __hip_atomic_fetch_add(p, (unsigned long long)(long long)(acc.x * scale), __ATOMIC_RELAXED,
-                                 __HIP_MEMORY_SCOPE_AGENT);
-          __hip_atomic_fetch_add(p + 1, (unsigned long long)(long long)(acc.y * scale), __ATOMIC_RELAXED,
-                                 __HIP_MEMORY_SCOPE_AGENT);
+          __hip_atomic_fetch_add(acc_out + (size_t)(xcc_id() & (kAccRegions - 1)) * T + off + k0 + m,
+                                 pack_sum(acc, scale), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         } else {
           partial[(size_t)(off + k0 + m) * nblk + blk] = acc;
         }
@@ -1287,8 +1287,7 @@ hipError_t iter_rows(hipStream_t s, const IterArgs& a) {
   if (a.fg.seg_w > NT * Q || !a.acc_in || !a.acc_out || !a.acc_zero || a.T < 1) return hipErrorInvalidValue;
   dim3 grid(a.fg.nseg, (a.fg.ny + ROWS - 1) / ROWS, a.B);
   hipLaunchKernelGGL((k_iter<NT, Q, TPL, FRACT, ROWS>), grid, dim3(NT * ROWS), 0, s, a.B == 1 ? a.one : HoloDesc{}, a.coef,
-                     a.st_in, (const ulonglong2*)a.acc_in, a.hd, a.st_out, (ulonglong2*)a.acc_out,
-                     (ulonglong2*)a.acc_zero, a.T, a.acc_scale, a.acc_unscale, a.stats, a.kstat, a.stat_stride,
+                     a.st_in, a.acc_in, a.hd, a.st_out, a.acc_out, a.acc_zero, a.T, a.acc_scale, a.acc_unscale, a.stats, a.kstat, a.stat_stride,
                      a.upd, a.flag, a.fg.nx, a.fg.ny, a.fg.seg_w, a.phase);
   return hipGetLastError();
 }
@@ -1399,13 +1398,13 @@ hipError_t launch_reduce(hipStream_t s, int B, int mmax, int nblk, float inv_n, 
 hipError_t launch_finish(hipStream_t s, int B, int T, const unsigned long long* acc, float unscale,
                          const HoloDesc* hd, const TrapState* st, float* V, float* stats, int kstat,
                          int stat_stride) {
-  hipLaunchKernelGGL(k_finish, dim3(B), dim3(256), 0, s, (const ulonglong2*)acc, T, unscale, hd, st, V, stats,
+  hipLaunchKernelGGL(k_finish, dim3(B), dim3(256), 0, s, acc, T, unscale, hd, st, V, stats,
                      kstat, stat_stride);
   return hipGetLastError();
 }
 
 hipError_t launch_collect(hipStream_t s, int T, const unsigned long long* acc, float unscale, float* V) {
-  hipLaunchKernelGGL(k_collect, dim3((T + 255) / 256), dim3(256), 0, s, (const ulonglong2*)acc, T, unscale, V);
+  hipLaunchKernelGGL(k_collect, dim3((T + 255) / 256), dim3(256), 0, s, acc, T, unscale, V);
   return hipGetLastError();
 }
 
@@ -1453,8 +1452,7 @@ hipError_t sep_t(hipStream_t s, const SepArgs& a) {
   if (MODE == 0 && (!a.acc_in || !a.acc_out || !a.acc_zero || a.T < 1)) return hipErrorInvalidValue;
   hipLaunchKernelGGL((k_sep<W, MODE, FRACT>), grid, dim3(W * 64), lds, s, a.coef, a.hd, a.st_in, a.st_out, a.vin,
                      a.stats, a.kstat, a.stat_stride, a.upd, a.flag, a.nx, a.ny, a.inv_n, a.sc, a.phase, a.grad,
-                     a.partial, (const ulonglong2*)a.acc_in, (ulonglong2*)a.acc_out, (ulonglong2*)a.acc_zero, a.T,
-                     a.acc_scale, a.acc_unscale);
+                     a.partial, a.acc_in, a.acc_out, a.acc_zero, a.T, a.acc_scale, a.acc_unscale);
   return hipGetLastError();
 }
 
