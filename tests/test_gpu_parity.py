@@ -143,8 +143,10 @@ def test_1024sq_256_traps_sampled(ctx):
 
 @pytest.mark.parametrize("n,m", [(2048, 6), (4096, 4)])
 def test_largest_grids_fixed_point_sums(ctx, n, m):
-    """The iteration kernel's 64-bit fixed-point trap sums at the largest grids (scale 2^39 at
-    2048^2, 2^37 at 4096^2, the smallest the library uses): one GS iteration, phase and V in full."""
+    """The iteration kernel's fixed-point trap sums (re and im as 32-bit integers in one 64-bit
+    word) at the largest grids: scale 2^8 at 2048^2 and 2^6 at 4096^2, the coarsest the library
+    uses, with 8192 and 32768 blocks each adding its rounding.  One GS iteration, phase and V in
+    full."""
     p = W.random_problem(450 + n, n, n, m, 1)
     g = run(ctx, "gs", p)
     o = oracle_solve("gs", p, p.iters)
