@@ -157,14 +157,17 @@ __device__ __forceinline__ unsigned long long pack_sum(float2 v, float scale) {
   const int re = (int)__builtin_rintf(v.x * scale), im = (int)__builtin_rintf(v.y * scale);
   return (unsigned long long)(long long)re + ((unsigned long long)(unsigned)im << 32);
 }
+static_assert(kAccRegions == 8, "VAcc sums eight regions");
 struct VAcc {
   const unsigned long long* __restrict__ acc;
   int T, off;
   float unscale;
   __device__ float2 operator()(int k) const {
-    unsigned long long w = 0;
+    unsigned long long w8[kAccRegions];
 #pragma unroll
-    for (int r = 0; r < kAccRegions; ++r) w += acc[(size_t)r * T + off + k];
+    for (int r = 0; r < kAccRegions; ++r) w8[r] = acc[(size_t)r * T + off + k];
+    // a tree of adds (exact, so the order is free): three dependent steps instead of seven
+    const unsigned long long w = ((w8[0] + w8[1]) + (w8[2] + w8[3])) + ((w8[4] + w8[5]) + (w8[6] + w8[7]));
     const int re = (int)(unsigned)w;
     const int im = (int)((unsigned)(w >> 32) - (unsigned)(re >> 31));
     return make_float2((float)re * unscale, (float)im * unscale);
@@ -177,7 +180,9 @@ struct VAcc {
 //   mode 0: no update; 1 (GS): theta_m <- arg V_m; 2 (GSW): also w_m <- w_m <|V|>/|V_m|
 // emit(m, state) is called once per trap m, by the thread that owns it.  <|V|> = 0 leaves
 // the state unchanged and raises *flag (if non-null).  With PRE, trap threadIdx.x's V and state
-// come from vpre / spre (loaded earlier by the caller) instead of memory.
+// come from vpre / spre (loaded earlier by the caller) instead of memory.  |V_m|, <|V|> and the
+// weight factor use the hardware square root and reciprocal (about 1 ulp each): this sits on the
+// critical path at the start of every iteration launch.
 template <int NT, class VGet, class Emit, bool PRE = false>
 __device__ void update_traps(VGet vmem, const TrapState* __restrict__ st_in, int off, int M, int mode, float* sh,
                              float* stats_row, int* flag, Emit emit, float2 vpre = make_float2(0.0f, 0.0f),
@@ -191,7 +196,7 @@ __device__ void update_traps(VGet vmem, const TrapState* __restrict__ st_in, int
     const float2 v = getv(k);
     const float vr = v.x, vi = v.y;
     const float I = vr * vr + vi * vi;
-    sa += sqrtf(I);
+    sa += __builtin_amdgcn_sqrtf(I);
     si += I;
     mx = fmaxf(mx, I);
     mn = fminf(mn, I);
@@ -201,7 +206,7 @@ __device__ void update_traps(VGet vmem, const TrapState* __restrict__ st_in, int
   } else {
     block_sum<NT>(sh, sa);  // the update needs only <|V|>
   }
-  const float mean_abs = sa / (float)M;
+  const float mean_abs = sa * __builtin_amdgcn_rcpf((float)M);
   if (stats_row) {
     const float mu = si / (float)M;
     float var = 0.0f, z0 = 0.0f, z1 = 0.0f, z2 = 0.0f;
@@ -227,9 +232,9 @@ __device__ void update_traps(VGet vmem, const TrapState* __restrict__ st_in, int
     if (mode != 0 && !degenerate) {
       const float2 v = getv(k);
       const float vr = v.x, vi = v.y;
-      const float amp = sqrtf(vr * vr + vi * vi);
+      const float amp = __builtin_amdgcn_sqrtf(vr * vr + vi * vi);
       const bool tiny = amp < floor_abs;
-      if (mode == 2) s.w *= mean_abs / (tiny ? floor_abs : amp);
+      if (mode == 2) s.w *= mean_abs * __builtin_amdgcn_rcpf(tiny ? floor_abs : amp);
       if (!tiny) {
         const float th = phase_of(vi, vr);  // arg V in [0, 2pi], kept in (-pi, pi]
         s.theta_rad = th > 3.14159265358979324f ? th - kTwoPi : th;
