@@ -387,6 +387,23 @@ def test_bad_arguments_on_gpu(hot, ctx):
         ctx.hot_rs(W.Slm(0, 4), p.xyz, p.theta0)
 
 
+def test_tuning_rejects_unsupported_shapes(hot):
+    """Every launch-shape knob accepts only the shapes the library has kernels for; a refused value
+    leaves the context usable with its previous settings."""
+    with hot.Context(0) as c:
+        for knob, val in (("pixels_per_lane", 3), ("traps_per_lane", 7), ("traps_per_lane", 9),
+                          ("segment", 32), ("sep_waves", 3), ("rows", 3)):
+            with pytest.raises(hot.HotError) as e:
+                c.set_tuning(**{knob: val})
+            assert e.value.code == hot.HOT_EINVAL, knob
+        c.set_tuning(traps_per_lane=8)
+        p = W.random_problem(392, 96, 40, 11, 3)
+        g = run(c, "gsw", p)
+    o = oracle_solve("gsw", p, p.iters)
+    assert_phase(to_np(g.phase), o["phi"])
+    assert_V(to_np(g.V), o["V"])
+
+
 def test_graph_replays_match_eager(hot):
     """The cached hipGraph of a solve, replayed several times with other eager work and
     synchronisations in between, reproduces the eager launch sequence bit for bit each time."""
