@@ -184,8 +184,8 @@ uint64_t splitmix64_next(uint64_t& s) {
 // Trap-pass lane layout for a hologram of m traps on a row segment of len pixels, for a
 // block of W waves and tpl traps per lane: each wave = a slices x g trap lanes.  Returns an
 // estimate of the block's cycles: per chunk of g*tpl traps, every lane walks its slice
-// (slen pixels, rounded up to a pair, x tpl terms x 36 issue cycles, or the LDS read when tpl is
-// small), then the block syncs and sums the S = W*a slice partials of each trap.
+// (slen pixels x tpl terms x 36 issue cycles, or the LDS read when tpl is small), then the
+// block syncs and sums the S = W*a slice partials of each trap.
 double layout_cost(int m, int len, int W, int tpl, int amax_cap, int& g, int& a) {
   int amax = std::max(1, std::min(16, len / (8 * W)));
   if (amax_cap > 0) amax = std::min(amax, amax_cap);
@@ -195,7 +195,7 @@ double layout_cost(int m, int len, int W, int tpl, int amax_cap, int& g, int& a)
   for (int gg = 1; gg <= 64; ++gg) {
     const int aa = std::min(64 / gg, amax);
     const int S = W * aa;
-    const int slen = (len + S - 1) / S + ((len + S - 1) / S & 1);  // pixels go in pairs
+    const int slen = (len + S - 1) / S;
     const int chunks = (m + gg * tpl - 1) / (gg * tpl);
     const int outs_per_thread = (gg * tpl + 64 * W - 1) / (64 * W);
     const double step = std::max(36.0 * tpl, 32.0);

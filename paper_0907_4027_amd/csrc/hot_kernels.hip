@@ -399,8 +399,16 @@ __device__ __forceinline__ void trap_pass_block(const TrapCoef* __restrict__ cf,
     }
     // Two pixels per half step, from two register pairs that alternate: one pair is summed while
     // the next is read (offsets hidden from the optimiser as in the pixel pass).  Full double
-    // steps run while 4 pixels remain, then at most 3.  Reads reach at most mine[slen + 1],
-    // inside px (S * slen + 3 entries); the pixel past an odd slice end gets mask 0.
+    // steps run while 4 pixels remain, then the last 1-3 pixels one pair and one single at a
+    // time.  Reads reach at most mine[slen + 1], inside px (S * slen + 3 entries).
+    auto term1 = [&](const float4& p0) {
+#pragma unroll
+      for (int k = 0; k < TPL; ++k) {
+        const float ta = to_period<FRACT>(__builtin_fmaf(ng[k], p0.z, __builtin_fmaf(na[k], p0.y, p0.x)));
+        accr[k] = __builtin_fmaf(p0.w, __builtin_amdgcn_cosf(ta), accr[k]);
+        acci[k] = __builtin_fmaf(p0.w, __builtin_amdgcn_sinf(ta), acci[k]);
+      }
+    };
     auto terms = [&](const float4& p0, const float4& p1) {
 #pragma unroll
       for (int k = 0; k < TPL; ++k) {
@@ -428,18 +436,13 @@ __device__ __forceinline__ void trap_pass_block(const TrapCoef* __restrict__ cf,
       __builtin_amdgcn_sched_barrier(0);
       terms(pc, pd);
     }
-    if (j < slen) {
-      const bool two = j + 2 < slen;
-      if (two) {
-        pc = mine[j + 2];
-        pd = mine[j + 3];
-      }
-      if (j + 1 >= slen) pb.w = 0.0f;
+    const int rest = slen - j;  // 0..3 pixels left, pa and pb already read
+    if (rest >= 2) {
+      if (rest == 3) pc = mine[j + 2];
       terms(pa, pb);
-      if (two) {
-        if (j + 3 >= slen) pd.w = 0.0f;
-        terms(pc, pd);
-      }
+      if (rest == 3) term1(pc);
+    } else if (rest == 1) {
+      term1(pa);
     }
     __syncthreads();  // red[] is free: earlier readers (previous chunk, or the pixel pass) are done
     if (active) {
