@@ -516,7 +516,7 @@ int solve(hot_ctx* c, const hot_slm* slm, int B, const int32_t* counts, const do
   const float inv_n = (float)(1.0 / (double)P.n);
   const int upd = algo == kGSW ? 2 : 1;
 
-  // The K-iteration launch sequence (2 kernels per iteration on the on-the-fly path).
+  // The K-iteration launch sequence (one kernel per iteration on the fused paths, four on the stored one).
   auto enqueue = [&](hipStream_t s) -> hipError_t {
     hipError_t e = hipSuccess;
     if (separable) {

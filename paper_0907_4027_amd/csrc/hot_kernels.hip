@@ -12,8 +12,10 @@
 // from the previous V, so no grid-wide synchronisation is needed), the pixel pass with
 // one lane per pixel, and -- with the fresh phases handed over through LDS -- the trap
 // pass with traps on lanes and pixels in a loop, so each lane accumulates its own V_m
-// over a slice of pixels and no per-trap cross-lane reduction is needed.  A small
-// second kernel sums the per-block partials in a fixed order.
+// over a slice of pixels and no per-trap cross-lane reduction is needed.  Each block adds
+// its per-trap sums as exact fixed-point integers to accumulators that the next launch
+// reads, so V does not depend on the order of the blocks and no reduction kernel runs
+// between iterations.
 //
 // All phases are in revolutions (see hot_internal.h).  sin/cos are the hardware
 // V_SIN_F32 / V_COS_F32, which take revolutions; their domain is |x| < 256, and the
