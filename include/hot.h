@@ -115,9 +115,13 @@ enum hot_tuning_key {
                                    of 16 x 16 pixels */
   HOT_TUNE_SEP_CHUNK = 7,       /* separable variant: traps whose tables a block holds in LDS at
                                    once, a multiple of 16 (more are streamed in chunks of this size) */
-  HOT_TUNE_ROWS = 8             /* on-the-fly iteration kernel: rows per block, 1 or 2 (two rows share
+  HOT_TUNE_ROWS = 8,            /* on-the-fly iteration kernel: rows per block, 1 or 2 (two rows share
                                    one GS/GSW update and one set of trap-sum additions; 256-thread
                                    rows only) */
+  HOT_TUNE_SEP_SPLIT = 9        /* separable iteration: waves per 16 x 16 tile, 1 or 2 (two take half
+                                   of the traps each and add their pixel sums in a fixed order;
+                                   default: two when the grid has at most one block per compute
+                                   unit, else one) */
 };
 int hot_set_tuning(hot_ctx* ctx, int key, int value);
 

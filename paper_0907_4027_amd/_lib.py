@@ -15,7 +15,7 @@ HOT_OK, HOT_EINVAL, HOT_ENOMEM, HOT_EDEVICE, HOT_EDEGENERATE = 0, -1, -2, -3, -4
 HOT_ONTHEFLY, HOT_STORED, HOT_SEPARABLE = 0, 1, 2
 HOT_MAX_TRAPS, HOT_MAX_SIDE, HOT_MAX_BATCH = 2048, 4096, 4096
 HOT_TUNE_PIXELS_PER_LANE, HOT_TUNE_TRAPS_PER_LANE, HOT_TUNE_SEGMENT, HOT_TUNE_SLICES, HOT_TUNE_GRAPHS = 1, 2, 3, 4, 5
-HOT_TUNE_SEP_WAVES, HOT_TUNE_SEP_CHUNK, HOT_TUNE_ROWS = 6, 7, 8
+HOT_TUNE_SEP_WAVES, HOT_TUNE_SEP_CHUNK, HOT_TUNE_ROWS, HOT_TUNE_SEP_SPLIT = 6, 7, 8, 9
 
 # every symbol include/hot.h declares
 EXPORTS = ("hot_create", "hot_destroy", "hot_set_stream", "hot_set_variant", "hot_set_tuning", "hot_sync", "hot_check_problem",

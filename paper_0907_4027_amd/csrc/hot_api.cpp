@@ -64,6 +64,7 @@ struct hot_ctx {
   hipStream_t own_stream = nullptr;
   int variant = HOT_ONTHEFLY;
   int tune_q = 0, tune_tpl = 0, tune_seg = 0, tune_amax = 0, tune_sepw = 0, tune_sepc = 0, tune_rows = 0;
+  int tune_sepk = 0;
   int use_graphs = 1;
   // captured launch sequences of solve(), keyed by everything they bake in (shapes, pointers)
   struct GraphEntry {
@@ -242,6 +243,7 @@ struct Plan {
   int nblk_stored = 0;
   // separable variant: blocks of 16 rows x 16 sep_w columns, sep_sc traps per LDS super-chunk
   int sep_w = 4, nblk_sep = 0, sep_sc = 16;
+  int sep_kh = 1;  // waves per 16 x 16 tile in the separable iteration (2: each takes half of the traps)
   // direct path fixed point: scale 2^s with s = 61 - ceil(log2 N); every block sum and every
   // trap's total has magnitude <= N, so no sum leaves +-2^61
   float acc_scale = 0.0f, acc_unscale = 0.0f;
@@ -310,11 +312,15 @@ int prepare(hot_ctx* c, const hot_slm* slm, int B, const int32_t* counts, const 
     }
     P.sep_w = w;
     P.nblk_sep = ((slm->nx + 16 * w - 1) / (16 * w)) * rows;
+    // two waves per tile when the grid has at most one block per compute unit (one wave per
+    // SIMD otherwise); a larger grid already has two resident blocks per unit, and the split
+    // only adds the exchange of the pixel sums (measured slower there)
+    P.sep_kh = c->tune_sepk > 0 ? c->tune_sepk : (int64_t)P.nblk_sep * B <= 256 ? 2 : 1;
     // traps per LDS super-chunk: all of them when they fit, with room for a second resident
     // block per compute unit when the grid has more blocks than compute units
     const int mp = (P.mmax + 15) / 16 * 16;
-    const size_t row_bytes = sep_lds_bytes(w, 16, P.mmax) - sep_lds_bytes(w, 0, P.mmax);  // per 16 traps
-    const size_t fixed = sep_lds_bytes(w, 0, P.mmax);
+    const size_t row_bytes = sep_lds_bytes(w, 16, P.mmax, P.sep_kh) - sep_lds_bytes(w, 0, P.mmax, P.sep_kh);
+    const size_t fixed = sep_lds_bytes(w, 0, P.mmax, P.sep_kh);
     int sc = 16;
     for (int bpc : {2, 1}) {
       if (bpc == 2 && (int64_t)P.nblk_sep * B <= 256) continue;
@@ -448,6 +454,7 @@ SepArgs sep_args(hot_ctx* c, const Plan& P, int mode, float* phase, int K) {
   a.ny = P.ny;
   a.mmax = P.mmax;
   a.sc = P.sep_sc;
+  a.kh = mode == 0 ? P.sep_kh : 1;
   a.fract = P.fract;
   a.coef = (const TrapCoef*)c->coef.p;
   a.hd = (const HoloDesc*)c->hd.p;
@@ -575,7 +582,7 @@ int solve(hot_ctx* c, const hot_slm* slm, int B, const int32_t* counts, const do
   if (c->use_graphs) {
     std::vector<uint64_t> key = {(uint64_t)B, (uint64_t)P.T, (uint64_t)P.nx, (uint64_t)P.ny, (uint64_t)K,
                                  (uint64_t)algo, (uint64_t)variant, (uint64_t)P.fract, (uint64_t)P.nt, (uint64_t)P.q,
-                                 (uint64_t)P.tpl, (uint64_t)P.fg.seg_w, (uint64_t)P.sep_w, (uint64_t)P.sep_sc,
+                                 (uint64_t)P.tpl, (uint64_t)P.fg.seg_w, (uint64_t)P.sep_w, (uint64_t)P.sep_sc, (uint64_t)P.sep_kh,
                                  (uint64_t)P.rows, (uint64_t)(uintptr_t)phase,
                                  (uint64_t)(uintptr_t)V, (uint64_t)(uintptr_t)w_out, (uint64_t)(uintptr_t)theta_out,
                                  (uint64_t)(uintptr_t)c->coef.p, (uint64_t)(uintptr_t)c->st.p,
@@ -751,6 +758,10 @@ int hot_set_tuning(hot_ctx* c, int key, int value) {
     case HOT_TUNE_SEP_WAVES:
       if (value != 0 && value != 1 && value != 2 && value != 4) return fail(HOT_EINVAL, "separable waves must be 0, 1, 2 or 4");
       c->tune_sepw = value;
+      return HOT_OK;
+    case HOT_TUNE_SEP_SPLIT:
+      if (value != 0 && value != 1 && value != 2) return fail(HOT_EINVAL, "separable waves per tile must be 0, 1 or 2");
+      c->tune_sepk = value;
       return HOT_OK;
     case HOT_TUNE_SEP_CHUNK:
       if (value < 0 || value > HOT_MAX_TRAPS || value % 16 != 0)

@@ -127,9 +127,10 @@ hipError_t launch_forward_stored(hipStream_t s, int n, int B, const float2* A, c
 // factors are computed in LDS from coef.
 struct SepArgs {
   int mode = 0;  // 0 iteration, 1 trap pass from `phase`, 2 pixel pass, 3 adjoint (G in vin, grad out)
-  int W = 4;     // waves per block: a block covers 16 rows x 16 W columns
+  int W = 4;     // tiles per block: a block covers 16 rows x 16 W columns
+  int kh = 1;    // mode 0: waves per tile (1, or 2 taking half of the traps each)
   int B = 1, nx = 0, ny = 0, mmax = 0;
-  int sc = 16;   // traps per LDS super-chunk (multiple of 16); sep_lds_bytes(W, sc, mmax) <= kSepLdsMax
+  int sc = 16;   // traps per LDS super-chunk (multiple of 16); sep_lds_bytes(W, sc, mmax, kh) <= kSepLdsMax
   bool fract = false;
   const TrapCoef* coef = nullptr;
   const HoloDesc* hd = nullptr;
@@ -156,11 +157,12 @@ struct SepArgs {
 };
 hipError_t launch_sep(hipStream_t s, const SepArgs& a);
 // dynamic LDS of a separable launch: per-trap coefficients and weights, the tables of sc traps
-// for the block's 16 W columns and 16 rows (plain and weighted), and W per-wave trap sums
+// for the block's 16 W columns and 16 rows (plain and weighted), W kh per-wave trap sums, and
+// with kh = 2 the waves' partial pixel sums (2 KB per wave)
 constexpr int kSepLdsMax = 160 * 1024 - 1024;
-inline size_t sep_lds_bytes(int W, int sc, int mmax) {
+inline size_t sep_lds_bytes(int W, int sc, int mmax, int kh = 1) {
   const size_t mp = (size_t)(mmax + 15) / 16 * 16;
-  return 24 * mp + 8 * (size_t)(sc + 2) * (16 * W + 32) + 8 * (size_t)W * sc;
+  return 24 * mp + 8 * (size_t)(sc + 2) * (16 * W + 32) + 8 * (size_t)W * kh * sc + (kh == 2 ? 2048 * (size_t)W * kh : 0);
 }
 
 // 8-bit SLM frame encoding.

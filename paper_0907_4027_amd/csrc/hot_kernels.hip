@@ -876,7 +876,8 @@ k_forward_stored(const float2* __restrict__ A, const float2* __restrict__ E, con
 // MFMA 16x16x4 operands: lane l = i + 16 k holds A[i][k] and B[k][i]; result D[i][j] is in
 // lane j + 16 (i / 4), register i % 4.
 //
-// A block owns 16 rows x 16 W columns of the SLM, one wave per 16 x 16 tile:
+// A block owns 16 rows x 16 W columns of the SLM, one wave per 16 x 16 tile (or, in the
+// iteration, two waves per tile that split the traps, so that two waves share each SIMD):
 //   pixel pass  D = X^T (columns x traps) . (c Y) (traps x rows); lane (j, g) ends with the
 //               four pixels (row0 + j, col0 + 4 g + v), v = 0..3, in its four registers
 //   epilogue    E = S / |S| = e^{i phase} of those pixels, kept in registers (and the phase,
@@ -1006,20 +1007,25 @@ __device__ __forceinline__ void trap_tiles(const float2* xc, const float2* yc, i
 // MODE 1: trap pass alone from the given phase (Eq. 1): per-block partials
 // MODE 2: pixel pass alone from the given state (phase out)
 // MODE 3: adjoint of Eq. 1: weights G_m (vin), grad[j] = (1/N) Im(e^{-i phi_j} S_j) for the given phase
-// Grid (ceil(nx / 16 W), ceil(ny / 16), B); sc = traps per super-chunk (a multiple of 16);
-// dynamic LDS sep_lds_bytes(W, sc, Mmax).
-template <int W, int MODE, bool FRACT>
-__global__ void __launch_bounds__(W * 64)
+// KH = 2 (MODE 0): two waves per tile, each taking half of the k-steps of the pixel pass and half
+//   of the trap tiles of the trap pass; the two partial pixel sums meet in LDS and are added in
+//   a fixed order (first half + second half), so both waves hold the same S, and the phase is
+//   written by the first.  Twice the waves per SIMD, the same work.
+// Grid (ceil(nx / 16 W), ceil(ny / 16), B), W KH waves per block; sc = traps per super-chunk (a
+// multiple of 16); dynamic LDS sep_lds_bytes(W, sc, Mmax, KH).
+template <int W, int MODE, bool FRACT, int KH>
+__global__ void __launch_bounds__(W * KH * 64)
 k_sep(const TrapCoef* __restrict__ coef, const HoloDesc* __restrict__ hd, const TrapState* __restrict__ st_in,
       TrapState* __restrict__ st_out, const float* __restrict__ vin, float* __restrict__ stats, int kstat,
       int stat_stride, int upd, int* __restrict__ flag, int nx, int ny, float inv_n, int sc,
       float* __restrict__ phase, float* __restrict__ grad, float2* __restrict__ partial,
       const unsigned long long* __restrict__ acc_in, unsigned long long* __restrict__ acc_out,
       unsigned long long* __restrict__ acc_zero, int T, float scale, float unscale) {
-  constexpr int NT = W * 64, CW = 16 * W;
+  static_assert(KH == 1 || (KH == 2 && MODE == 0), "trap halves are built for the iteration only");
+  constexpr int NW = W * KH, NT = NW * 64, CW = 16 * W;
   constexpr bool kPixel = MODE != 1, kTrap = MODE <= 1;
   extern __shared__ float4 lds4[];
-  __shared__ float sh[8 * W];
+  __shared__ float sh[8 * NW];
   const int b = blockIdx.z;
   const int M = hd[b].m, off = hd[b].off;
   const int Mp = (M + 15) & ~15;
@@ -1029,11 +1035,13 @@ k_sep(const TrapCoef* __restrict__ coef, const HoloDesc* __restrict__ hd, const 
   float2* xt = cw + Mp;                                  // [CW][XS] X_m(c)
   float2* yt = xt + CW * XS;                             // [16][XS] Y_m(r)
   float2* ywt = yt + 16 * XS;                            // [16][XS] c_m Y_m(r)
-  float2* red = ywt + 16 * XS;                           // [W][sc] per-wave trap sums
+  float2* red = ywt + 16 * XS;                           // [NW][sc] per-wave trap sums
+  float4* sx = reinterpret_cast<float4*>(red + NW * sc);  // KH = 2: [NW][64][2] partial pixel sums
 
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, li = lane & 15, g = lane >> 4;
+  const int tw = wave % W, half = wave / W;  // the wave's tile, and its share of the traps
   const int row0 = blockIdx.y * 16, cb = blockIdx.x * CW;
-  const int c0 = cb + wave * 16;
+  const int c0 = cb + tw * 16;
   const int r = row0 + li;
   const size_t pix0 = (size_t)b * nx * ny + (size_t)r * nx + c0 + 4 * g;  // pixel (r, c0 + 4 g)
   bool in[4];
@@ -1042,29 +1050,30 @@ k_sep(const TrapCoef* __restrict__ coef, const HoloDesc* __restrict__ hd, const 
   float er[4], ei[4];
 
   // tables of traps [k0, k0 + n) into LDS: lane j keeps trap k0 + j's coefficients in registers
-  // while its wave walks the block's columns wave, wave + W, ... (tables_x) or rows wave, wave + W,
-  // ... (tables_y).  Columns past nx and rows past ny take the coordinates of the last column
+  // while its wave walks the block's columns wave, wave + NW, ... (tables_x) or rows wave,
+  // wave + NW, ... (tables_y).  Columns past nx and rows past ny take the coordinates of the last column
   // and row (finite entries inside the sin/cos domain; such pixels have E = 0), and traps past M
   // are left as the formula gives them (c_m = 0, partials never written), so none of them reach
   // V or the phase.
-  float xu[16], xu2[16], yv[16 / W], yv2[16 / W];
+  static_assert(16 % NW == 0, "rows of a block split evenly over its waves");
+  float xu[16 / KH], xu2[16 / KH], yv[16 / NW], yv2[16 / NW];
 #pragma unroll
-  for (int i = 0; i < 16; ++i) {
-    xu[i] = (float)(2 * min(cb + wave + i * W, nx - 1) - (nx - 1));
+  for (int i = 0; i < 16 / KH; ++i) {
+    xu[i] = (float)(2 * min(cb + wave + i * NW, nx - 1) - (nx - 1));
     xu2[i] = xu[i] * xu[i];
   }
 #pragma unroll
-  for (int i = 0; i < 16 / W; ++i) {
-    yv[i] = (float)(2 * min(row0 + wave + i * W, ny - 1) - (ny - 1));
+  for (int i = 0; i < 16 / NW; ++i) {
+    yv[i] = (float)(2 * min(row0 + wave + i * NW, ny - 1) - (ny - 1));
     yv2[i] = yv[i] * yv[i];
   }
   auto tables_x = [&](int k0, int n) {
     for (int j = lane; j < n; j += 64) {
       const float4 k = cf[k0 + j];
 #pragma unroll
-      for (int i = 0; i < 16; ++i) {
+      for (int i = 0; i < 16 / KH; ++i) {
         const float t = to_period<FRACT>(__builtin_fmaf(k.y, xu2[i], k.x * xu[i]));
-        xt[(wave + i * W) * XS + j] = make_float2(__builtin_amdgcn_cosf(t), __builtin_amdgcn_sinf(t));
+        xt[(wave + i * NW) * XS + j] = make_float2(__builtin_amdgcn_cosf(t), __builtin_amdgcn_sinf(t));
       }
     }
   };
@@ -1073,11 +1082,11 @@ k_sep(const TrapCoef* __restrict__ coef, const HoloDesc* __restrict__ hd, const 
       const float4 k = cf[k0 + j];
       const float2 w = weighted ? cw[k0 + j] : make_float2(0.0f, 0.0f);
 #pragma unroll
-      for (int i = 0; i < 16 / W; ++i) {
+      for (int i = 0; i < 16 / NW; ++i) {
         const float t = to_period<FRACT>(__builtin_fmaf(k.y, yv2[i], k.z * yv[i]));
         const float2 v = make_float2(__builtin_amdgcn_cosf(t), __builtin_amdgcn_sinf(t));
-        yt[(wave + i * W) * XS + j] = v;
-        if (weighted) ywt[(wave + i * W) * XS + j] = cmul(w, v);
+        yt[(wave + i * NW) * XS + j] = v;
+        if (weighted) ywt[(wave + i * NW) * XS + j] = cmul(w, v);
       }
     }
   };
@@ -1136,7 +1145,7 @@ k_sep(const TrapCoef* __restrict__ coef, const HoloDesc* __restrict__ hd, const 
   if constexpr (kPixel) {
     // S^T[c][r] = sum_m X[m][c] (c_m Y[m][r])
     f32x4 sre = {0.0f, 0.0f, 0.0f, 0.0f}, sim = sre;
-    const float2* xrow = xt + (wave * 16 + li) * XS;
+    const float2* xrow = xt + (tw * 16 + li) * XS;
     const float2* yrow = ywt + li * XS;
     for (int s = 0; s < nsc; ++s) {
       const int k0 = s * sc, n = min(sc, Mp - k0);
@@ -1146,25 +1155,35 @@ k_sep(const TrapCoef* __restrict__ coef, const HoloDesc* __restrict__ hd, const 
       }
       tables_y(k0, n, true);
       __syncthreads();
-      const int ksteps = (min(n, M - k0) + 3) / 4;  // traps past M add nothing: skip them
-      const int nfull = ksteps / 8;                  // groups of 32 traps, operands double-buffered
+      int ksteps = (min(n, M - k0) + 3) / 4;  // traps past M add nothing: skip them
+      const float2* xs0 = xrow;
+      const float2* ys0 = yrow;
+      if constexpr (KH == 2) {  // the first half takes k-steps [0, kh), the second [kh, ksteps)
+        const int kh = (ksteps + 1) / 2;
+        if (half == 1) {
+          xs0 += 4 * kh;
+          ys0 += 4 * kh;
+        }
+        ksteps = half == 0 ? kh : ksteps - kh;
+      }
+      const int nfull = ksteps / 8;  // groups of 32 traps, operands double-buffered
       PixelOps<8> ga, gb;
-      if (nfull > 0) ga.load(xrow + 8 * g, yrow + 8 * g);
+      if (nfull > 0) ga.load(xs0 + 8 * g, ys0 + 8 * g);
       int q = 0;
       for (; q + 2 <= nfull; q += 2) {
-        gb.load(xrow + 32 * (q + 1) + 8 * g, yrow + 32 * (q + 1) + 8 * g);
+        gb.load(xs0 + 32 * (q + 1) + 8 * g, ys0 + 32 * (q + 1) + 8 * g);
         __builtin_amdgcn_sched_barrier(0);
         ga.mma(sre, sim);
         __builtin_amdgcn_sched_barrier(0);
-        if (q + 2 < nfull) ga.load(xrow + 32 * (q + 2) + 8 * g, yrow + 32 * (q + 2) + 8 * g);
+        if (q + 2 < nfull) ga.load(xs0 + 32 * (q + 2) + 8 * g, ys0 + 32 * (q + 2) + 8 * g);
         __builtin_amdgcn_sched_barrier(0);
         gb.mma(sre, sim);
         __builtin_amdgcn_sched_barrier(0);
       }
       if (q < nfull) ga.mma(sre, sim);
       const int base = 32 * nfull, nk = ksteps - 8 * nfull;
-      const float2* xr = xrow + base + nk * g;
-      const float2* yr = yrow + base + nk * g;
+      const float2* xr = xs0 + base + nk * g;
+      const float2* yr = ys0 + base + nk * g;
       switch (nk) {
         case 1: pixel_tail<1>(xr, yr, sre, sim); break;
         case 2: pixel_tail<2>(xr, yr, sre, sim); break;
@@ -1176,6 +1195,15 @@ k_sep(const TrapCoef* __restrict__ coef, const HoloDesc* __restrict__ hd, const 
         default: break;
       }
     }
+    if constexpr (KH == 2) {
+      sx[(wave * 64 + lane) * 2] = make_float4(sre[0], sre[1], sre[2], sre[3]);
+      sx[(wave * 64 + lane) * 2 + 1] = make_float4(sim[0], sim[1], sim[2], sim[3]);
+      __syncthreads();
+      const float4 r0 = sx[(tw * 64 + lane) * 2], i0 = sx[(tw * 64 + lane) * 2 + 1];
+      const float4 r1 = sx[((W + tw) * 64 + lane) * 2], i1 = sx[((W + tw) * 64 + lane) * 2 + 1];
+      sre = f32x4{r0.x + r1.x, r0.y + r1.y, r0.z + r1.z, r0.w + r1.w};
+      sim = f32x4{i0.x + i1.x, i0.y + i1.y, i0.z + i1.z, i0.w + i1.w};
+    }
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
       if constexpr (MODE == 3) {
@@ -1185,7 +1213,7 @@ k_sep(const TrapCoef* __restrict__ coef, const HoloDesc* __restrict__ hd, const 
               inv_n * (__builtin_amdgcn_cosf(pr) * sim[v] - __builtin_amdgcn_sinf(pr) * sre[v]);  // Im(e^{-i phi} S)
         }
       } else {
-        if (phase != nullptr && in[v]) phase[pix0 + v] = phase_of(sim[v], sre[v]);
+        if (phase != nullptr && in[v] && half == 0) phase[pix0 + v] = phase_of(sim[v], sre[v]);
         const float n2 = sre[v] * sre[v] + sim[v] * sim[v];
         float cr = 1.0f, ci = 0.0f;  // arg 0 = 0
         if (n2 >= 1.17549435e-38f) {
@@ -1213,7 +1241,7 @@ k_sep(const TrapCoef* __restrict__ coef, const HoloDesc* __restrict__ hd, const 
   if constexpr (kTrap) {
     // per tile of 16 traps: T^T[r][m] = sum_c E[r][c] conj X[m][c], then sum_r conj Y[m][r] T^T[r][m]
     const int nblk = gridDim.x * gridDim.y, blk = blockIdx.y * gridDim.x + blockIdx.x;
-    const float2* xcol = xt + (wave * 16 + 4 * g) * XS + li;
+    const float2* xcol = xt + (tw * 16 + 4 * g) * XS + li;
     const float2* ycol = yt + (4 * g) * XS + li;
     for (int s = 0; s < nsc; ++s) {
       const int k0 = s * sc, n = min(sc, Mp - k0);
@@ -1223,9 +1251,12 @@ k_sep(const TrapCoef* __restrict__ coef, const HoloDesc* __restrict__ hd, const 
         tables_y(k0, n, false);
         __syncthreads();
       }
-      int t = 0;
-      for (; t + 128 <= n; t += 128) trap_tiles<8>(xcol + t, ycol + t, XS, er, ei, g, red + wave * sc + t + li);
-      switch ((n - t) / 16) {
+      // KH = 2: the first half takes tiles [0, th) of 16 traps, the second [th, n / 16)
+      const int th = KH == 2 ? (n / 16 + 1) / 2 : n / 16;
+      int t = KH == 2 && half == 1 ? 16 * th : 0;
+      const int tend = KH == 2 && half == 0 ? 16 * th : n;
+      for (; t + 128 <= tend; t += 128) trap_tiles<8>(xcol + t, ycol + t, XS, er, ei, g, red + wave * sc + t + li);
+      switch ((tend - t) / 16) {
         case 1: trap_tiles<1>(xcol + t, ycol + t, XS, er, ei, g, red + wave * sc + t + li); break;
         case 2: trap_tiles<2>(xcol + t, ycol + t, XS, er, ei, g, red + wave * sc + t + li); break;
         case 3: trap_tiles<3>(xcol + t, ycol + t, XS, er, ei, g, red + wave * sc + t + li); break;
@@ -1237,11 +1268,12 @@ k_sep(const TrapCoef* __restrict__ coef, const HoloDesc* __restrict__ hd, const 
       }
       __syncthreads();
       for (int m = threadIdx.x; m < n && k0 + m < M; m += NT) {
-        float2 acc = red[m];
+        const float2* rm = red + (KH == 2 && m >= 16 * th ? W * sc : 0) + m;  // the half that took m
+        float2 acc = rm[0];
 #pragma unroll
         for (int w = 1; w < W; ++w) {
-          acc.x += red[w * sc + m].x;
-          acc.y += red[w * sc + m].y;
+          acc.x += rm[w * sc].x;
+          acc.y += rm[w * sc].y;
         }
         if constexpr (MODE == 0) {
           __hip_atomic_fetch_add(acc_out + (size_t)(xcc_id() & (kAccRegions - 1)) * T + off + k0 + m,
@@ -1450,29 +1482,29 @@ hipError_t launch_forward_stored(hipStream_t s, int n, int B, const float2* A, c
   return hipGetLastError();
 }
 
-template <int W, int MODE, bool FRACT>
+template <int W, int MODE, bool FRACT, int KH>
 hipError_t sep_t(hipStream_t s, const SepArgs& a) {
   // raise the kernel's dynamic LDS limit once, to everything the static part leaves
-  static const hipError_t attr = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_sep<W, MODE, FRACT>),
+  static const hipError_t attr = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_sep<W, MODE, FRACT, KH>),
                                                      hipFuncAttributeMaxDynamicSharedMemorySize, kSepLdsMax);
   if (attr != hipSuccess) return attr;
-  const size_t lds = sep_lds_bytes(W, a.sc, a.mmax);
+  const size_t lds = sep_lds_bytes(W, a.sc, a.mmax, KH);
   if (lds > (size_t)kSepLdsMax) return hipErrorInvalidValue;
   dim3 grid(a.gx(), a.gy(), a.B);
   if (MODE == 0 && (!a.acc_in || !a.acc_out || !a.acc_zero || a.T < 1)) return hipErrorInvalidValue;
-  hipLaunchKernelGGL((k_sep<W, MODE, FRACT>), grid, dim3(W * 64), lds, s, a.coef, a.hd, a.st_in, a.st_out, a.vin,
-                     a.stats, a.kstat, a.stat_stride, a.upd, a.flag, a.nx, a.ny, a.inv_n, a.sc, a.phase, a.grad,
-                     a.partial, a.acc_in, a.acc_out, a.acc_zero, a.T, a.acc_scale, a.acc_unscale);
+  hipLaunchKernelGGL((k_sep<W, MODE, FRACT, KH>), grid, dim3(W * KH * 64), lds, s, a.coef, a.hd, a.st_in, a.st_out,
+                     a.vin, a.stats, a.kstat, a.stat_stride, a.upd, a.flag, a.nx, a.ny, a.inv_n, a.sc, a.phase,
+                     a.grad, a.partial, a.acc_in, a.acc_out, a.acc_zero, a.T, a.acc_scale, a.acc_unscale);
   return hipGetLastError();
 }
 
 template <int W, bool FRACT>
 hipError_t sep_mode(hipStream_t s, const SepArgs& a) {
   switch (a.mode) {
-    case 0: return sep_t<W, 0, FRACT>(s, a);
-    case 1: return sep_t<W, 1, FRACT>(s, a);
-    case 2: return sep_t<W, 2, FRACT>(s, a);
-    case 3: return sep_t<W, 3, FRACT>(s, a);
+    case 0: return a.kh == 2 ? sep_t<W, 0, FRACT, 2>(s, a) : sep_t<W, 0, FRACT, 1>(s, a);
+    case 1: return sep_t<W, 1, FRACT, 1>(s, a);
+    case 2: return sep_t<W, 2, FRACT, 1>(s, a);
+    case 3: return sep_t<W, 3, FRACT, 1>(s, a);
     default: return hipErrorInvalidValue;
   }
 }
@@ -1484,6 +1516,7 @@ hipError_t sep_fract(hipStream_t s, const SepArgs& a) {
 
 hipError_t launch_sep(hipStream_t s, const SepArgs& a) {
   if (a.W != 1 && a.W != 2 && a.W != 4) return hipErrorInvalidValue;
+  if (a.kh != 1 && a.kh != 2) return hipErrorInvalidValue;
   if (a.nx < 1 || a.ny < 1 || a.mmax < 1 || a.mmax > kMaxTraps || a.sc < 16 || a.sc % 16 != 0)
     return hipErrorInvalidValue;
   switch (a.W) {

@@ -87,12 +87,13 @@ class Context:
         check(self._lib, self._lib.hot_set_variant(self._ctx, int(v)))
 
     def set_tuning(self, pixels_per_lane: int = 0, traps_per_lane: int = 0, segment: int = 0,
-                   slices: int = 0, sep_waves: int = 0, sep_chunk: int = 0, rows: int = 0) -> None:
+                   slices: int = 0, sep_waves: int = 0, sep_chunk: int = 0, rows: int = 0,
+                   sep_split: int = 0) -> None:
         """Launch-shape knobs (0 = built-in choice); see hot_set_tuning in include/hot.h."""
         for key, val in ((_lib.HOT_TUNE_PIXELS_PER_LANE, pixels_per_lane), (_lib.HOT_TUNE_TRAPS_PER_LANE, traps_per_lane),
                          (_lib.HOT_TUNE_SEGMENT, segment), (_lib.HOT_TUNE_SLICES, slices),
                          (_lib.HOT_TUNE_SEP_WAVES, sep_waves), (_lib.HOT_TUNE_SEP_CHUNK, sep_chunk),
-                         (_lib.HOT_TUNE_ROWS, rows)):
+                         (_lib.HOT_TUNE_ROWS, rows), (_lib.HOT_TUNE_SEP_SPLIT, sep_split)):
             check(self._lib, self._lib.hot_set_tuning(self._ctx, key, int(val)))
 
     def set_graphs(self, enabled: bool) -> None:

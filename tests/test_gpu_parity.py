@@ -392,7 +392,7 @@ def test_tuning_rejects_unsupported_shapes(hot):
     leaves the context usable with its previous settings."""
     with hot.Context(0) as c:
         for knob, val in (("pixels_per_lane", 3), ("traps_per_lane", 7), ("traps_per_lane", 9),
-                          ("segment", 32), ("sep_waves", 3), ("rows", 3)):
+                          ("segment", 32), ("sep_waves", 3), ("rows", 3), ("sep_split", 3)):
             with pytest.raises(hot.HotError) as e:
                 c.set_tuning(**{knob: val})
             assert e.value.code == hot.HOT_EINVAL, knob
@@ -503,15 +503,17 @@ def test_separable_matches_oracle(sep, name, algo):
     assert_stats(g.stats, o["stats"])
 
 
-@pytest.mark.parametrize("waves,chunk", [(1, 0), (2, 0), (4, 0), (4, 32), (2, 16), (1, 48)])
-def test_separable_every_block_width(hot, waves, chunk):
-    """Blocks of 1, 2 and 4 waves (16 x 16 W pixels), with all traps resident in LDS or streamed in
-    super-chunks of 16, 32 or 48, give the oracle's answer; the grid is ragged in both directions
-    and M = 70 leaves a partial trap tile."""
+@pytest.mark.parametrize("waves,chunk,split", [(1, 0, 0), (2, 0, 0), (4, 0, 0), (4, 32, 0), (2, 16, 0), (1, 48, 0),
+                                               (4, 0, 1), (2, 16, 1), (1, 48, 1)])
+def test_separable_every_block_width(hot, waves, chunk, split):
+    """Blocks of 1, 2 and 4 tiles (16 x 16 W pixels), with all traps resident in LDS or streamed in
+    super-chunks of 16, 32 or 48, and one or two waves per tile, give the oracle's answer; the grid
+    is ragged in both directions and M = 70 leaves a partial trap tile (with chunks of 16 the
+    second wave of a tile gets no trap tile of its own)."""
     p = W.random_problem(430, 200, 90, 70, 5)
     with hot.Context(0) as c:
         c.set_variant("separable")
-        c.set_tuning(sep_waves=waves, sep_chunk=chunk)
+        c.set_tuning(sep_waves=waves, sep_chunk=chunk, sep_split=split)
         g = run(c, "gsw", p)
     o = oracle_solve("gsw", p, p.iters)
     assert_phase(to_np(g.phase), o["phi"])
