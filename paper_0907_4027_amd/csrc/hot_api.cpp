@@ -323,7 +323,8 @@ int prepare(hot_ctx* c, const hot_slm* slm, int B, const int32_t* counts, const 
     const size_t fixed = sep_lds_bytes(w, 0, P.mmax, P.sep_kh);
     int sc = 16;
     for (int bpc : {2, 1}) {
-      if (bpc == 2 && (int64_t)P.nblk_sep * B <= 256) continue;
+      // (a block of more than four waves already fills its compute unit's registers)
+      if (bpc == 2 && ((int64_t)P.nblk_sep * B <= 256 || w * P.sep_kh > 4)) continue;
       const size_t budget = (size_t)kSepLdsMax / bpc;
       if (budget <= fixed + row_bytes) continue;
       sc = (int)std::min<size_t>(mp / 16, (budget - fixed) / row_bytes) * 16;
