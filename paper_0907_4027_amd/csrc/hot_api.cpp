@@ -75,7 +75,7 @@ struct hot_ctx {
   std::vector<GraphEntry> graphs;
   uint64_t graph_clock = 0;
   DevBuf coef, st, hd, partial, stats, flag, amat, efield;
-  DevBuf acc;  // direct path: 3 rotating buffers of fixed-point trap sums [kAccRegions][T][2] u64
+  DevBuf acc;  // fused paths: 3 rotating buffers of fixed-point trap sums [kAccRegions][T] u64 (re + 2^32 im)
   Staging ring[kRing];
   int ring_pos = 0;
   int* flag_host = nullptr;  // pinned
