@@ -564,7 +564,8 @@ int solve(hot_ctx* c, const hot_slm* slm, int B, const int32_t* counts, const do
         if (e == hipSuccess)
           e = launch_backward_stored(s, P.n, B, (const float2*)c->amat.p, st[k & 1], hd, phase, (float2*)c->efield.p);
         if (e == hipSuccess)
-          e = launch_forward_stored(s, P.n, B, (const float2*)c->amat.p, (const float2*)c->efield.p, hd, part);
+          e = launch_forward_stored(s, P.n, B, P.mmax, (const float2*)c->amat.p, (const float2*)c->efield.p, hd,
+                                    part);
         if (e == hipSuccess) e = launch_reduce(s, B, P.mmax, nblk, inv_n, part, hd, V);
       }
     }
@@ -945,7 +946,8 @@ int hot_time_passes(hot_ctx* c, const hot_slm* slm, int32_t M, const double* xyz
     hipError_t e = launch_backward_stored(c->stream, P.n, 1, (const float2*)c->amat.p, st[0], hd, phase,
                                           (float2*)c->efield.p);
     if (e != hipSuccess) return e;
-    return launch_forward_stored(c->stream, P.n, 1, (const float2*)c->amat.p, (const float2*)c->efield.p, hd, part);
+    return launch_forward_stored(c->stream, P.n, 1, P.mmax, (const float2*)c->amat.p, (const float2*)c->efield.p, hd,
+                                 part);
   };
   // group 1: the reduction to V (per iteration on the stored path; once per solve, from the
   // fixed-point sums, on the fused paths)
@@ -982,8 +984,8 @@ int hot_time_passes(hot_ctx* c, const hot_slm* slm, int32_t M, const double* xyz
   };
   auto g3 = [&]() {
     if (separable) return sep_mode(1);
-    return stored ? launch_forward_stored(c->stream, P.n, 1, (const float2*)c->amat.p, (const float2*)c->efield.p, hd,
-                                          part)
+    return stored ? launch_forward_stored(c->stream, P.n, 1, P.mmax, (const float2*)c->amat.p,
+                                          (const float2*)c->efield.p, hd, part)
                   : launch_forward(c->stream, P.fgf, 1, P.tplf, P.fract, coef, hd + 1, phase, part);
   };
   hipEvent_t ev[5];

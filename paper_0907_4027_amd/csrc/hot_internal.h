@@ -120,8 +120,8 @@ hipError_t launch_expdelta(hipStream_t s, int nx, int ny, int B, int mmax, bool 
                            const HoloDesc* hd, float2* A);
 hipError_t launch_backward_stored(hipStream_t s, int n, int B, const float2* A, const TrapState* st,
                                   const HoloDesc* hd, float* phase, float2* E);
-hipError_t launch_forward_stored(hipStream_t s, int n, int B, const float2* A, const float2* E, const HoloDesc* hd,
-                                 float2* partial);
+hipError_t launch_forward_stored(hipStream_t s, int n, int B, int mmax, const float2* A, const float2* E,
+                                 const HoloDesc* hd, float2* partial);
 
 // Separable reformulation on the matrix cores (any batch); the per-block tables of Eq. 2's two
 // factors are computed in LDS from coef.

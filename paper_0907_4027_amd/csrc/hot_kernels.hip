@@ -825,18 +825,24 @@ k_backward_stored(const float2* __restrict__ A, const TrapState* __restrict__ st
   E[(size_t)b * n + j] = make_float2(__builtin_amdgcn_cosf(pr), __builtin_amdgcn_sinf(pr));
 }
 
-// Per wave: 64 * PPL pixels (PPL per lane, kept in registers); for each trap the wave sums
-// conj(A[m][j]) E_j over its pixels and writes one partial per (trap, wave).
+// Per wave: 64 * PPL pixels (PPL per lane, kept in registers); for each trap of its group the
+// wave sums conj(A[m][j]) E_j over its pixels and writes one partial per (trap, wave).  Grid x =
+// pixel blocks x tg trap groups: a hologram's traps are split into tg contiguous groups so that
+// enough waves stream A at once to keep HBM busy (each (trap, pixel block) is still one wave).
 template <int PPL>
 __global__ void __launch_bounds__(kBlock)
 k_forward_stored(const float2* __restrict__ A, const float2* __restrict__ E, const HoloDesc* __restrict__ hd, int n,
-                 float2* __restrict__ partial) {
+                 int tg, float2* __restrict__ partial) {
   const int b = blockIdx.y;
   const int M = hd[b].m, off = hd[b].off;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int nblk = (n + 64 * PPL - 1) / (64 * PPL);
-  const int blk = blockIdx.x * 4 + wave;
-  if (blk >= nblk) return;
+  const int nbx = (nblk + 3) / 4;
+  const int grp = (int)blockIdx.x / nbx;
+  const int blk = ((int)blockIdx.x - grp * nbx) * 4 + wave;
+  const int mg = (M + tg - 1) / tg;
+  const int m0 = grp * mg, m1 = min(M, m0 + mg);
+  if (blk >= nblk || m0 >= m1) return;
   const int j0 = blk * 64 * PPL + lane;
   float er[PPL], ei[PPL];
 #pragma unroll
@@ -846,7 +852,7 @@ k_forward_stored(const float2* __restrict__ A, const float2* __restrict__ E, con
     er[p] = e.x;
     ei[p] = e.y;
   }
-  for (int m = 0; m < M; ++m) {
+  for (int m = m0; m < m1; ++m) {
     const float2* __restrict__ row = A + (size_t)(off + m) * n;
     float sr = 0.0f, si = 0.0f;
 #pragma unroll
@@ -1474,11 +1480,13 @@ hipError_t launch_backward_stored(hipStream_t s, int n, int B, const float2* A, 
   return hipGetLastError();
 }
 
-hipError_t launch_forward_stored(hipStream_t s, int n, int B, const float2* A, const float2* E, const HoloDesc* hd,
-                                 float2* partial) {
+hipError_t launch_forward_stored(hipStream_t s, int n, int B, int mmax, const float2* A, const float2* E,
+                                 const HoloDesc* hd, float2* partial) {
   const int nblk = stored_nblk(n);
-  dim3 grid((nblk + 3) / 4, B);
-  hipLaunchKernelGGL(k_forward_stored<kStoredPpl>, grid, dim3(kBlock), 0, s, A, E, hd, n, partial);
+  // trap groups: about 4096 waves in all (four per SIMD), at most one per trap
+  const int tg = std::max(1, std::min({mmax, 16, (4096 + nblk * B - 1) / (nblk * B)}));
+  dim3 grid((nblk + 3) / 4 * tg, B);
+  hipLaunchKernelGGL(k_forward_stored<kStoredPpl>, grid, dim3(kBlock), 0, s, A, E, hd, n, tg, partial);
   return hipGetLastError();
 }
 

@@ -272,6 +272,21 @@ def test_stored_variant_matches_oracle(hot, algo):
     assert_stats(g.stats, o["stats"])
 
 
+@pytest.mark.parametrize("nx,ny,m", [(70, 33, 3), (300, 200, 131), (512, 512, 100)])
+def test_stored_trap_groups(hot, nx, ny, m):
+    """The stored trap pass splits a hologram's traps into groups over the grid (up to 16, at most
+    one per trap; the last groups of an uneven split are empty): every (trap, pixel block) partial
+    is written once, whatever the split."""
+    p = W.random_problem(335 + m, nx, ny, m, 3)
+    with hot.Context(0) as c:
+        c.set_variant("stored")
+        g = run(c, "gsw", p)
+    o = oracle_solve("gsw", p, p.iters)
+    assert_phase(to_np(g.phase), o["phi"])
+    assert_V(to_np(g.V), o["V"])
+    assert_stats(g.stats, o["stats"])
+
+
 # ------------------------------------------------------------------ invariants, determinism, edges
 
 def test_single_trap_closed_form(ctx):
