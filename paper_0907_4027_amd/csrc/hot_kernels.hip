@@ -812,7 +812,7 @@ k_backward_stored(const float2* __restrict__ A, const TrapState* __restrict__ st
   if (j >= n) return;
   const float2* __restrict__ col = A + (size_t)off * n + j;
   float sr = 0.0f, si = 0.0f;
-#pragma unroll 8
+#pragma unroll 16
   for (int m = 0; m < M; ++m) {
     const float2 v = col[(size_t)m * n];
     const float2 k = cm[m];
