@@ -95,8 +95,8 @@ def main():
                     help="run one section only (for profiler runs)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU: the solver runs on a single MI355X; multi-GPU sharding is "
-              "described in DESIGN.md but not built (pass --gpus 1)", file=sys.stderr)
+        print("bench.py measures one GPU: the solver runs on a single MI355X; sharding a batch or one "
+              "hologram's rows over several GPUs is not built (pass --gpus 1)", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
