@@ -111,8 +111,8 @@ enum hot_tuning_key {
   HOT_TUNE_SLICES = 4,          /* trap pass: at most this many pixel slices per wave, 1..16 */
   HOT_TUNE_GRAPHS = 5,          /* 1 (default): replay a captured hipGraph of a solve's launch
                                    sequence when shapes and buffers repeat; 0: launch eagerly */
-  HOT_TUNE_SEP_WAVES = 6,       /* separable variant: waves per block (1, 2 or 4), each wave a tile
-                                   of 16 x 16 pixels */
+  HOT_TUNE_SEP_WAVES = 6,       /* separable variant: tiles of 16 x 16 pixels per block (1, 2 or 4),
+                                   one or two waves each (HOT_TUNE_SEP_SPLIT) */
   HOT_TUNE_SEP_CHUNK = 7,       /* separable variant: traps whose tables a block holds in LDS at
                                    once, a multiple of 16 (more are streamed in chunks of this size) */
   HOT_TUNE_ROWS = 8,            /* on-the-fly iteration kernel: rows per block, 1 or 2 (two rows share
