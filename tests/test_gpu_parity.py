@@ -419,12 +419,16 @@ def test_tuning_rejects_unsupported_shapes(hot):
     assert_V(to_np(g.V), o["V"])
 
 
-def test_graph_replays_match_eager(hot):
+@pytest.mark.parametrize("variant", ["onthefly", "separable", "stored"])
+def test_graph_replays_match_eager(hot, variant):
     """The cached hipGraph of a solve, replayed several times with other eager work and
-    synchronisations in between, reproduces the eager launch sequence bit for bit each time."""
+    synchronisations in between, reproduces the eager launch sequence bit for bit each time, for
+    each kernel family (the separable one with two waves per tile at these grids)."""
     p = W.c2()
     q = W.random_problem(400, 300, 77, 37, 4)
     with hot.Context(0) as eager, hot.Context(0) as graphed:
+        eager.set_variant(variant)
+        graphed.set_variant(variant)
         eager.set_graphs(False)
         ref = eager.hot_gsw(p.slm, p.xyz, p.theta0, 6, state=True)
         ref_q = eager.hot_gsw(q.slm, q.xyz, q.theta0, q.iters)
