@@ -320,21 +320,29 @@ def test_mirror_symmetry(ctx, iters):
             assert abs(A[4 * j + i] - A[4 * j + 3 - i]) <= 1e-4 * A[4 * j + i]
 
 
-def test_resume_is_bitwise(ctx):
+@pytest.mark.parametrize("variant", ["onthefly", "separable", "stored"])
+def test_resume_is_bitwise(hot, variant):
+    """K1 iterations, then K2 more started from the exported (w, theta), equal K1 + K2 at once."""
     p = W.random_problem(350, 256, 256, 24)
-    full = ctx.hot_gsw(p.slm, p.xyz, p.theta0, 9)
-    a = ctx.hot_gsw(p.slm, p.xyz, p.theta0, 4, state=True)
-    b = ctx.hot_gsw(p.slm, p.xyz, to_np(a.theta), 5, w0=a.w.clone())
-    torch.cuda.synchronize()
+    with hot.Context(0) as ctx:
+        ctx.set_variant(variant)
+        full = ctx.hot_gsw(p.slm, p.xyz, p.theta0, 9)
+        a = ctx.hot_gsw(p.slm, p.xyz, p.theta0, 4, state=True)
+        b = ctx.hot_gsw(p.slm, p.xyz, to_np(a.theta), 5, w0=a.w.clone())
+        torch.cuda.synchronize()
     assert torch.equal(full.phase, b.phase)
     assert torch.equal(full.V, b.V)
 
 
-def test_runs_are_bitwise_deterministic(ctx):
+@pytest.mark.parametrize("variant", ["onthefly", "separable", "stored"])
+def test_runs_are_bitwise_deterministic(hot, variant):
+    """Two runs give the same bits: every sum has a fixed order or is an exact integer sum."""
     p = W.c2()
-    a = ctx.hot_gsw(p.slm, p.xyz, p.theta0, 5)
-    b = ctx.hot_gsw(p.slm, p.xyz, p.theta0, 5)
-    torch.cuda.synchronize()
+    with hot.Context(0) as ctx:
+        ctx.set_variant(variant)
+        a = ctx.hot_gsw(p.slm, p.xyz, p.theta0, 5)
+        b = ctx.hot_gsw(p.slm, p.xyz, p.theta0, 5)
+        torch.cuda.synchronize()
     assert torch.equal(a.phase, b.phase) and torch.equal(a.V, b.V)
 
 
