@@ -355,13 +355,16 @@ def test_seeded_theta_matches_splitmix(ctx):
     assert_V(to_np(g.V), o["V"])
 
 
-def test_large_phase_range_uses_explicit_reduction(ctx):
+@pytest.mark.parametrize("variant", ["onthefly", "separable", "stored"])
+def test_large_phase_range_uses_explicit_reduction(hot, variant):
     """Traps 0.4-0.6 mm off axis push |Delta| past the hardware sin/cos domain (256 rev): the
-    explicit fract() path must keep parity."""
+    explicit fract() path of each kernel family must keep parity."""
     rng = np.random.default_rng(370)
     xyz = np.column_stack([rng.uniform(4e-4, 6e-4, 6), rng.uniform(-6e-4, -4e-4, 6), rng.uniform(-1e-5, 1e-5, 6)])
     p = W.Problem(W.Slm(256, 256), xyz, rng.uniform(0, 2 * math.pi, 6), 4)
-    g = run(ctx, "gsw", p)
+    with hot.Context(0) as ctx:
+        ctx.set_variant(variant)
+        g = run(ctx, "gsw", p)
     o = oracle.solve("gsw", p.slm, p.xyz, p.theta0, p.iters)
     assert_phase(to_np(g.phase), o["phi"], tol=3e-3)
     assert_V(to_np(g.V), o["V"], rtol=3e-4)
