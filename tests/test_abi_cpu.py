@@ -30,6 +30,20 @@ def test_header_and_binding_agree():
     assert declared_functions() == sorted(_lib.EXPORTS)
 
 
+def test_header_constants_match_binding():
+    """Every enum and #define constant the header gives (error codes, variants, tuning keys, limits)
+    has the same value in the binding."""
+    text = re.sub(r"/\*.*?\*/", "", open(HEADER).read(), flags=re.S)
+    consts = {k: int(v) for k, v in re.findall(r"\b(HOT_[A-Z0-9_]+)\s*=\s*(-?\d+)", text)}
+    consts.update({k: int(v) for k, v in re.findall(r"#define\s+(HOT_[A-Z0-9_]+)\s+(-?\d+)", text)})
+    assert len(consts) >= 15
+    for name, value in consts.items():
+        if name == "HOT_ABI_VERSION":
+            continue
+        assert hasattr(_lib, name), name
+        assert getattr(_lib, name) == value, (name, getattr(_lib, name), value)
+
+
 def test_every_declared_symbol_is_exported(lib):
     for name in declared_functions():
         assert hasattr(lib, name), name
