@@ -82,6 +82,46 @@ def time_wall(fn, reps, sync):
     return (time.perf_counter() - t0) / reps * 1e3
 
 
+def measure_peaks(ctx, log):
+    """Issue rates of the FP32 vector pipes (FMA, sin/cos, and the direct passes' term mix) at 1, 2,
+    4 and 8 waves per SIMD with the shader clock each ran at, and the device copy bandwidth, all
+    from the library's probe kernels.  The roofline's peak assumes 2.4 GHz, one FMA per SIMD per 4
+    cycles and sin/cos at half that rate with no overlap (8 issue slots per term); the 'model' ratios
+    below compare each measured rate with that model at the measured clock."""
+    import torch
+    # shader cycles per lane operation in the model: a wave64 FMA takes 4, a sin or cos 8, a term
+    # (4 FMA + sin + cos) 32
+    kinds = {0: ("fma", 4.0 / 64), 1: ("sincos", 8.0 / 64), 2: ("term", 32.0 / 64)}
+    res = {}
+    simds = 256 * 4
+    for kind, (name, cyc_per_op) in kinds.items():
+        rows = {}
+        for wps in (1, 2, 4, 8):
+            reps = 40000 // wps
+            r = ctx.hot_probe_issue(kind, wps, reps)
+            model = simds * r["clock_hz"] / cyc_per_op   # lane operations per second per the model
+            model_24 = simds * 2.4e9 / cyc_per_op
+            rows[str(wps)] = {"ops_per_s": r["ops_per_s"], "clock_GHz": round(r["clock_hz"] / 1e9, 4),
+                              "vs_model_at_measured_clock": round(r["ops_per_s"] / model, 4),
+                              "vs_model_at_2.4GHz": round(r["ops_per_s"] / model_24, 4),
+                              "span_ms": round(r["span_s"] * 1e3, 3), "event_ms": round(r["event_s"] * 1e3, 3)}
+        res[name] = rows
+        log(f"[bench] probe {name}: " + "  ".join(
+            f"{w}w {v['ops_per_s'] / 1e12:.2f}T/s @{v['clock_GHz']:.2f}GHz ({v['vs_model_at_measured_clock']:.3f})"
+            for w, v in rows.items()))
+    nbytes = 1 << 30
+    src = torch.ones(nbytes // 4, device="cuda")
+    dst = torch.empty_like(src)
+    cp = ctx.hot_probe_copy(src, dst, reps=20)
+    del src, dst
+    res["copy"] = {"bytes": nbytes, "GBs_read_plus_write": round(cp["bytes_per_s"] / 1e9, 1),
+                   "ms_per_copy": round(cp["ms_per_copy"], 4), "frac_of_8TBs": round(cp["bytes_per_s"] / 8e12, 4)}
+    log(f"[bench] probe copy 1 GiB: {cp['bytes_per_s'] / 1e9:.0f} GB/s read+write")
+    res["model"] = {"fma_cycles_per_wave_instruction": 4, "sincos_cycles_per_wave_instruction": 8,
+                    "term_cycles_per_wave": 32, "peak_terms_per_s_at_2.4GHz": PEAK_TERMS_PER_S}
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -91,7 +131,7 @@ def main():
     ap.add_argument("--no-extra", action="store_true", help="skip batched / adjoint / stored comparisons")
     ap.add_argument("--no-tune", action="store_true", help="skip the autotuner's launch-shape sweep")
     ap.add_argument("--only", choices=["main", "passes", "tune", "batched", "adjoint", "stored", "interactive", "separable",
-                                       "fig7", "counters"], default=None,
+                                       "fig7", "counters", "peaks"], default=None,
                     help="run one section only (for profiler runs)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -421,6 +461,10 @@ def main():
                               "last_frame_efficiency": round(float(I.sum()), 4),
                               "last_frame_uniformity": round(float(1 - (I.max() - I.min()) / (I.max() + I.min())), 4)}
         log(f"[bench] interactive frame {lat.mean():.3f} ms mean, p99 {np.quantile(lat, 0.99):.3f} ms")
+
+    # ---------------------------------------------------------------- measured pipe rates behind the roofline
+    if args.only in (None, "peaks"):
+        out["peaks"] = measure_peaks(ctx, log)
 
     # ---------------------------------------------------------------- CPU oracle on a bounded sample
     cpu = None

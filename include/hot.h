@@ -105,7 +105,7 @@ int hot_set_variant(hot_ctx* ctx, int variant);
  * HOT_TUNE_GRAPHS).  They change how work is tiled or launched, never what is computed
  * beyond FP32 summation order. */
 enum hot_tuning_key {
-  HOT_TUNE_PIXELS_PER_LANE = 1, /* pixel pass: pixels per lane, 1, 2 or 4 */
+  HOT_TUNE_PIXELS_PER_LANE = 1, /* fused iteration kernel: pixels per lane, 1 or 2 */
   HOT_TUNE_TRAPS_PER_LANE = 2,  /* trap pass: traps each lane accumulates: 1..6 or 8 */
   HOT_TUNE_SEGMENT = 3,         /* trap pass: pixels of a row per block, 64..1024 */
   HOT_TUNE_SLICES = 4,          /* trap pass: at most this many pixel slices per wave, 1..16 */
@@ -118,10 +118,13 @@ enum hot_tuning_key {
   HOT_TUNE_ROWS = 8,            /* on-the-fly iteration kernel: rows per block, 1 or 2 (two rows share
                                    one GS/GSW update and one set of trap-sum additions; 256-thread
                                    rows only) */
-  HOT_TUNE_SEP_SPLIT = 9        /* separable iteration: waves per 16 x 16 tile, 1 or 2 (two take half
+  HOT_TUNE_SEP_SPLIT = 9,       /* separable iteration: waves per 16 x 16 tile, 1 or 2 (two take half
                                    of the traps each and add their pixel sums in a fixed order;
                                    default: two when the grid has at most one block per compute
                                    unit, else one) */
+  HOT_TUNE_FRACT = 10           /* direct passes: 1 reduces every per-term phase argument to one period
+                                   explicitly (one more instruction per term); 0 (default) does so
+                                   only when an argument could leave the hardware sin/cos domain */
 };
 int hot_set_tuning(hot_ctx* ctx, int key, int value);
 
@@ -213,6 +216,27 @@ int hot_encode_u8(hot_ctx* ctx, int64_t n, const float* phase, uint8_t* frame);
 int hot_time_passes(hot_ctx* ctx, const hot_slm* slm, int32_t M, const double* xyz, const double* theta0,
                     int32_t reps, float* phase, float* V, float* ms);
 
+/* Measurement aid: issue rate of the FP32 vector pipes that bound the direct passes.  Launches
+ * one block of 4 * waves_per_simd waves per compute unit (waves_per_simd 1, 2, 4 or 8), each wave
+ * running `reps` repetitions (1..2^24) of an unrolled instruction stream of one kind:
+ *   kind 0  FP32 FMA (128 per repetition, 8 independent chains)
+ *   kind 1  hardware sin/cos (128 per repetition, 8 independent chains)
+ *   kind 2  the term of the direct passes (16 per repetition): two FMAs form the phase
+ *           (Eq. 2 in revolutions), sin and cos, two FMAs accumulate (plus one add per repetition)
+ * after a short warm-up launch.  Writes, to host `out` (6 doubles):
+ *   out[0] operations per second: lane-level FMAs (kind 0), sin/cos (kind 1) or terms (kind 2),
+ *          over the span from the first wave's start to the last wave's end (s_memrealtime,
+ *          100 MHz); out[1] mean shader clock of the waves [Hz] (s_memtime cycles over the same
+ *          waves' real time); out[2] that span [s]; out[3] the launch's duration by HIP events [s];
+ *   out[4] mean shader cycles per wave; out[5] number of waves.
+ * Synchronises the context's stream; uses a small device buffer held by the context. */
+int hot_probe_issue(hot_ctx* ctx, int kind, int waves_per_simd, int64_t reps, double* out);
+
+/* Measurement aid: device memory bandwidth.  Copies `bytes` (a positive multiple of 16) from
+ * device `src` to device `dst` (not overlapping) `reps` times (1..1000) after one untimed copy,
+ * with a kernel of 16-byte vector loads and stores.  Writes to host `out` (2 doubles): out[0]
+ * bytes read plus bytes written per second, out[1] ms per copy (HIP events).  Synchronises. */
+int hot_probe_copy(hot_ctx* ctx, const void* src, void* dst, int64_t bytes, int reps, double* out);
 
 /* Message for the last non-OK return on this thread ("" if none). */
 const char* hot_last_error(void);

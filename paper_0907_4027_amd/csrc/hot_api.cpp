@@ -65,6 +65,7 @@ struct hot_ctx {
   int variant = HOT_ONTHEFLY;
   int tune_q = 0, tune_tpl = 0, tune_seg = 0, tune_amax = 0, tune_sepw = 0, tune_sepc = 0, tune_rows = 0;
   int tune_sepk = 0;
+  int tune_fract = 0;
   int use_graphs = 1;
   // captured launch sequences of solve(), keyed by everything they bake in (shapes, pointers)
   struct GraphEntry {
@@ -75,6 +76,7 @@ struct hot_ctx {
   std::vector<GraphEntry> graphs;
   uint64_t graph_clock = 0;
   DevBuf coef, st, hd, partial, stats, flag, amat, efield;
+  DevBuf probe;  // micro-benchmark sink and clock stamps
   DevBuf acc;  // fused paths: 3 rotating buffers of fixed-point trap sums [kAccRegions][T] u64 (re + 2^32 im)
   Staging ring[kRing];
   int ring_pos = 0;
@@ -244,8 +246,9 @@ struct Plan {
   // separable variant: blocks of 16 rows x 16 sep_w columns, sep_sc traps per LDS super-chunk
   int sep_w = 4, nblk_sep = 0, sep_sc = 16;
   int sep_kh = 1;  // waves per 16 x 16 tile in the separable iteration (2: each takes half of the traps)
-  // direct path fixed point: scale 2^s with s = 61 - ceil(log2 N); every block sum and every
-  // trap's total has magnitude <= N, so no sum leaves +-2^61
+  // fused paths' fixed point: scale 2^s with s = 30 - ceil(log2 N) (re and im as 32-bit integers in
+  // one 64-bit word); every block sum and every trap's total has magnitude <= N, so no sum of the
+  // scaled parts leaves +-2^30
   float acc_scale = 0.0f, acc_unscale = 0.0f;
 };
 
@@ -334,25 +337,29 @@ int prepare(hot_ctx* c, const hot_slm* slm, int B, const int32_t* counts, const 
     P.sep_sc = std::max(16, sc);
   }
 
+  // Eq. 2 in revolutions per pixel-index unit (hot_internal.h), in FP64; a and b are reduced to
+  // [-1/2, 1/2] (exact: U and V are integers, so a U and b V change by whole revolutions)
   const double lf = slm->wavelength * slm->focal;
   const double ca = slm->pitch / (2.0 * lf);
   const double cg = slm->pitch * slm->pitch / (8.0 * lf * slm->focal);
   c->h_coef.resize(P.T);
   c->h_st.resize(P.T);
   c->h_hd.resize(2 * (size_t)B);
-  const double umax = slm->nx - 1, vmax = slm->ny - 1;
-  double bound = 0.0, thmax = 1.0;
+  double gmax = 0.0, amax = 0.0;
   uint64_t sm = seed;
   for (int t = 0; t < P.T; ++t) {
     const double x = xyz[3 * t], y = xyz[3 * t + 1], z = xyz[3 * t + 2];
     TrapCoef k;
-    k.a = (float)(ca * x);
-    k.b = (float)(ca * y);
-    k.g = (float)(cg * z);
+    k.a = ca * x;
+    k.a -= std::rint(k.a);
+    k.b = ca * y;
+    k.b -= std::rint(k.b);
+    k.g = cg * z;
+    k.gf = (float)k.g;
     k.pad = 0.0f;
     c->h_coef[t] = k;
-    bound = std::max(bound, std::fabs((double)k.g) * (umax * umax + vmax * vmax) + std::fabs((double)k.a) * umax +
-                                std::fabs((double)k.b) * vmax);
+    gmax = std::max(gmax, std::fabs(k.g));
+    amax = std::max(amax, std::fabs(k.a) + 2.0 * std::fabs(k.g) * (slm->nx - 1));
     double th;
     if (seeded)
       th = 2.0 * kPi * (double)(splitmix64_next(sm) >> 40) * (1.0 / 16777216.0);
@@ -364,11 +371,16 @@ int prepare(hot_ctx* c, const hot_slm* slm, int B, const int32_t* counts, const 
     s.theta_rev = s.theta_rad * 0.159154943091895336f;
     s.w = 1.0f;
     s.pad = 0.0f;
-    thmax = std::max(thmax, std::fabs((double)s.theta_rev));
     c->h_st[t] = s;
   }
-  // keep |argument| of the hardware sin/cos inside its domain (|x| < 256 rev)
-  P.fract = bound + thmax + 2.0 > 240.0;
+  // Largest per-term argument of the direct passes, |g u^2 + a' u + C| with |a'| <= min(1/4, |a| + 2|g| Uc)
+  // (a' is reduced mod 1/2), |C| < 3/2 and |u| at most the widest block of any pass in U units (the
+  // fused iteration, the stand-alone pixel pass of kBlock pixels and the stand-alone trap pass).
+  // The hardware sin/cos take |x| < 256 rev; beyond a margin the passes reduce each argument
+  // explicitly (fract, one more instruction per term), as they do when the tuning knob asks.
+  const double umax = (double)std::max({P.fg.seg_w, P.fgf.seg_w, kBlock * 2});
+  const double bound = gmax * umax * umax + std::min(0.25, amax) * umax + 2.5;
+  P.fract = c->tune_fract == 1 || bound > 240.0;
   const int Wi = P.nt / 64, Wf = kBlock / 64;
   P.tpl = c->tune_tpl > 0 ? c->tune_tpl : choose_tpl(counts, B, P.fg.seg_w, Wi, c->tune_amax);
   P.tplf = c->tune_tpl > 0 ? c->tune_tpl : choose_tpl(counts, B, P.fgf.seg_w, Wf, c->tune_amax);
@@ -439,7 +451,7 @@ int ensure_stored(hot_ctx* c, const Plan& P) {
   if ((rc = ensure(c, c->efield, sizeof(float2) * (size_t)P.B * P.n))) return rc;
   if (!c->amat_valid || c->amat.cap < sizeof(float2) * (size_t)P.T * P.n) {
     if ((rc = ensure(c, c->amat, sizeof(float2) * (size_t)P.T * P.n))) return rc;
-    HIP_TRY(launch_expdelta(c->stream, P.nx, P.ny, P.B, P.mmax, P.fract, (const TrapCoef*)c->coef.p,
+    HIP_TRY(launch_expdelta(c->stream, P.nx, P.ny, P.B, P.mmax, (const TrapCoef*)c->coef.p,
                             (const HoloDesc*)c->hd.p, (float2*)c->amat.p));
     c->amat_valid = true;
   }
@@ -456,7 +468,6 @@ SepArgs sep_args(hot_ctx* c, const Plan& P, int mode, float* phase, int K) {
   a.mmax = P.mmax;
   a.sc = P.sep_sc;
   a.kh = mode == 0 ? P.sep_kh : 1;
-  a.fract = P.fract;
   a.coef = (const TrapCoef*)c->coef.p;
   a.hd = (const HoloDesc*)c->hd.p;
   a.stats = (float*)c->stats.p;
@@ -710,7 +721,8 @@ int hot_destroy(hot_ctx* c) {
   (void)hipSetDevice(c->device);
   (void)hipStreamSynchronize(c->stream);
   for (auto& g : c->graphs) (void)hipGraphExecDestroy(g.exec);
-  for (DevBuf* b : {&c->coef, &c->st, &c->hd, &c->partial, &c->stats, &c->flag, &c->amat, &c->efield, &c->acc})
+  for (DevBuf* b : {&c->coef, &c->st, &c->hd, &c->partial, &c->stats, &c->flag, &c->amat, &c->efield, &c->acc,
+                    &c->probe})
     if (b->p) (void)hipFree(b->p);
   for (auto& s : c->ring) {
     if (s.pending && s.ev) (void)hipEventSynchronize(s.ev);
@@ -741,7 +753,7 @@ int hot_set_tuning(hot_ctx* c, int key, int value) {
   if (!c) return fail(HOT_EINVAL, "ctx is NULL");
   switch (key) {
     case HOT_TUNE_PIXELS_PER_LANE:
-      if (value != 0 && value != 1 && value != 2 && value != 4) return fail(HOT_EINVAL, "pixels per lane must be 1, 2 or 4");
+      if (value != 0 && value != 1 && value != 2) return fail(HOT_EINVAL, "pixels per lane must be 0, 1 or 2");
       c->tune_q = value;
       return HOT_OK;
     case HOT_TUNE_TRAPS_PER_LANE:
@@ -773,6 +785,10 @@ int hot_set_tuning(hot_ctx* c, int key, int value) {
     case HOT_TUNE_ROWS:
       if (value != 0 && value != 1 && value != 2) return fail(HOT_EINVAL, "rows per block must be 0, 1 or 2");
       c->tune_rows = value;
+      return HOT_OK;
+    case HOT_TUNE_FRACT:
+      if (value != 0 && value != 1) return fail(HOT_EINVAL, "explicit reduction must be 0 (as needed) or 1 (always)");
+      c->tune_fract = value;
       return HOT_OK;
     case HOT_TUNE_SLICES:
       if (value < 0 || value > 16) return fail(HOT_EINVAL, "slices must be 0..16");
@@ -1022,6 +1038,106 @@ int hot_time_passes(hot_ctx* c, const hot_slm* slm, int32_t M, const double* xyz
   } while (0);
   for (auto& e : ev) (void)hipEventDestroy(e);
   return out;
+}
+
+int hot_probe_issue(hot_ctx* c, int kind, int waves_per_simd, int64_t reps, double* out) {
+  if (!c) return fail(HOT_EINVAL, "ctx is NULL");
+  if (kind < 0 || kind > 2) return fail(HOT_EINVAL, "probe kind %d outside 0..2", kind);
+  if (waves_per_simd != 1 && waves_per_simd != 2 && waves_per_simd != 4 && waves_per_simd != 8)
+    return fail(HOT_EINVAL, "waves per SIMD must be 1, 2, 4 or 8");
+  if (reps < 1 || reps > (1LL << 24)) return fail(HOT_EINVAL, "reps = %lld outside 1..2^24", (long long)reps);
+  if (!out) return fail(HOT_EINVAL, "out is NULL");
+  int rc;
+  if ((rc = set_dev(c))) return rc;
+  int cus = 0;
+  HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, c->device));
+  // one block of 4 * waves_per_simd waves per compute unit (two of 1024 threads for 8 waves)
+  const int threads = std::min(1024, 256 * waves_per_simd);
+  const int blocks = cus * (256 * waves_per_simd / threads);
+  const int waves = blocks * threads / 64;
+  const size_t sink_bytes = sizeof(float) * (size_t)blocks * threads;
+  if ((rc = ensure(c, c->probe, sink_bytes + 32 * (size_t)waves))) return rc;
+  float* sink = (float*)c->probe.p;
+  unsigned long long* stamps = (unsigned long long*)((char*)c->probe.p + sink_bytes);
+  hipEvent_t e0, e1;
+  HIP_TRY(hipEventCreate(&e0));
+  HIP_TRY(hipEventCreate(&e1));
+  int res = HOT_OK;
+  std::vector<unsigned long long> h(4 * (size_t)waves);
+  do {
+    // a short launch first (clocks ramp, code is loaded), then the measured one
+    if (launch_probe(c->stream, kind, blocks, threads, std::max<int64_t>(1, reps / 16), 1.0f, sink, stamps) !=
+            hipSuccess ||
+        hipEventRecord(e0, c->stream) != hipSuccess ||
+        launch_probe(c->stream, kind, blocks, threads, reps, 1.0f, sink, stamps) != hipSuccess ||
+        hipEventRecord(e1, c->stream) != hipSuccess) {
+      res = fail(HOT_EDEVICE, "probe launch failed");
+      break;
+    }
+    if (hipMemcpyAsync(h.data(), stamps, 32 * (size_t)waves, hipMemcpyDeviceToHost, c->stream) != hipSuccess ||
+        hipStreamSynchronize(c->stream) != hipSuccess) {
+      res = fail(HOT_EDEVICE, "probe read-back failed");
+      break;
+    }
+    float ev_ms = 0.0f;
+    (void)hipEventElapsedTime(&ev_ms, e0, e1);
+    unsigned long long rmin = ~0ull, rmax = 0;
+    double cyc = 0.0, clk = 0.0;
+    for (int w = 0; w < waves; ++w) {
+      const unsigned long long c0 = h[4 * w], c1 = h[4 * w + 1], r0 = h[4 * w + 2], r1 = h[4 * w + 3];
+      rmin = std::min(rmin, r0);
+      rmax = std::max(rmax, r1);
+      cyc += (double)(c1 - c0);
+      clk += r1 > r0 ? (double)(c1 - c0) / ((double)(r1 - r0) * 1e-8) : 0.0;
+    }
+    const double span = (double)(rmax - rmin) * 1e-8;  // s_memrealtime ticks at 100 MHz
+    const double ops = (double)waves * 64.0 * (double)reps * (double)probe_ops_per_rep(kind);
+    out[0] = span > 0.0 ? ops / span : 0.0;
+    out[1] = clk / waves;
+    out[2] = span;
+    out[3] = ev_ms * 1e-3;
+    out[4] = cyc / waves;
+    out[5] = (double)waves;
+  } while (0);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  return res;
+}
+
+int hot_probe_copy(hot_ctx* c, const void* src, void* dst, int64_t bytes, int reps, double* out) {
+  if (!c) return fail(HOT_EINVAL, "ctx is NULL");
+  if (!src || !dst || !out) return fail(HOT_EINVAL, "src, dst and out are required");
+  if (bytes < 16 || bytes % 16 != 0) return fail(HOT_EINVAL, "bytes must be a positive multiple of 16");
+  if (reps < 1 || reps > 1000) return fail(HOT_EINVAL, "reps = %d outside 1..1000", reps);
+  int rc;
+  if ((rc = set_dev(c))) return rc;
+  int cus = 0;
+  HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, c->device));
+  const size_t n16 = (size_t)bytes / 16;
+  const int blocks = (int)std::max<size_t>(1, std::min<size_t>((n16 + 1023) / 1024, (size_t)cus * 16));
+  hipEvent_t e0, e1;
+  HIP_TRY(hipEventCreate(&e0));
+  HIP_TRY(hipEventCreate(&e1));
+  int res = HOT_OK;
+  do {
+    if (launch_probe_copy(c->stream, src, dst, n16, blocks) != hipSuccess || hipEventRecord(e0, c->stream) != hipSuccess) {
+      res = fail(HOT_EDEVICE, "copy launch failed");
+      break;
+    }
+    for (int i = 0; i < reps && res == HOT_OK; ++i)
+      if (launch_probe_copy(c->stream, src, dst, n16, blocks) != hipSuccess) res = fail(HOT_EDEVICE, "copy launch failed");
+    if (res != HOT_OK || hipEventRecord(e1, c->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) {
+      if (res == HOT_OK) res = fail(HOT_EDEVICE, "copy timing failed");
+      break;
+    }
+    float ms = 0.0f;
+    (void)hipEventElapsedTime(&ms, e0, e1);
+    out[0] = ms > 0.0f ? 2.0 * (double)bytes * reps / (ms * 1e-3) : 0.0;  // bytes read + written per second
+    out[1] = ms / reps;
+  } while (0);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  return res;
 }
 
 }  // extern "C"

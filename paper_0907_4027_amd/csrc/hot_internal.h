@@ -11,16 +11,26 @@ namespace hot {
 // reduction of a phase to one period exact (fract of an FP32 value is exact) and
 // matches the input convention of the hardware sin/cos (sin(2 pi x)).
 //
-// Pixel coordinates are carried as exact integers in FP32:
+// Pixel coordinates are carried as exact integers:
 //   U_c = 2c - (nx-1),  V_r = 2r - (ny-1)  (so x = U pitch / 2, y = V pitch / 2),
 // and Eq. 2 divided by 2 pi becomes  Delta_rev = g (U^2 + V^2) + a U + b V  with
 //   a = pitch x_m / (2 lambda f),  b = pitch y_m / (2 lambda f),  g = pitch^2 z_m / (8 lambda f^2).
-// U^2 and V^2 are exact in FP32 for nx, ny <= 4096.
+// Since U and V are integers, a and b matter only modulo 1 (the host reduces them, exactly).
+//
+// Per-block reference.  A block of the direct passes covers pixels U = Uc + u of one row V, with
+// Uc the (integer) centre of its pixels and u = U - Uc even; there
+//   Delta_rev = g u^2 + a' u + K,   a' = a + 2 g Uc (mod 1/2),   K = g (Uc^2 + V^2) + a Uc + b V (mod 1).
+// a' and K are formed once per (trap, block) in FP64 from the FP64 coefficients and rounded once
+// to FP32, so the per-term FP32 argument g u^2 + a' u + K stays small (|u| <= the block's width
+// in U units) and the pixel pass (Eq. 3) and the trap pass (Eq. 1) see the same a' and K.
 
-// Per-trap constant coefficients, formed in FP64 on the host, rounded once.
+// Per-trap constant coefficients, formed in FP64 on the host (a, b reduced to [-1/2, 1/2)).
 struct alignas(16) TrapCoef {
-  float a, b, g, pad;
+  double a, b, g;  // revolutions per pixel-index unit, as above
+  float gf;        // g rounded to FP32: the lens coefficient of the per-term argument
+  float pad;
 };
+static_assert(sizeof(TrapCoef) == 32, "TrapCoef is two 16-byte words");
 
 // Per-trap iteration state, rewritten on the device by the weight/phase update.
 struct alignas(16) TrapState {
@@ -116,7 +126,7 @@ hipError_t launch_update(hipStream_t s, int B, const float* V, const HoloDesc* h
                          TrapState* st_out, float* stats, int kstat, int stat_stride, int mode, int* flag);
 
 // Stored-exp(i Delta) variant.
-hipError_t launch_expdelta(hipStream_t s, int nx, int ny, int B, int mmax, bool fract, const TrapCoef* coef,
+hipError_t launch_expdelta(hipStream_t s, int nx, int ny, int B, int mmax, const TrapCoef* coef,
                            const HoloDesc* hd, float2* A);
 hipError_t launch_backward_stored(hipStream_t s, int n, int B, const float2* A, const TrapState* st,
                                   const HoloDesc* hd, float* phase, float2* E);
@@ -131,7 +141,6 @@ struct SepArgs {
   int kh = 1;    // mode 0: waves per tile (1, or 2 taking half of the traps each)
   int B = 1, nx = 0, ny = 0, mmax = 0;
   int sc = 16;   // traps per LDS super-chunk (multiple of 16); sep_lds_bytes(W, sc, mmax, kh) <= kSepLdsMax
-  bool fract = false;
   const TrapCoef* coef = nullptr;
   const HoloDesc* hd = nullptr;
   const TrapState* st_in = nullptr;
@@ -156,14 +165,23 @@ struct SepArgs {
   int nblk() const { return gx() * gy(); }
 };
 hipError_t launch_sep(hipStream_t s, const SepArgs& a);
-// dynamic LDS of a separable launch: per-trap coefficients and weights, the tables of sc traps
-// for the block's 16 W columns and 16 rows (plain and weighted), W kh per-wave trap sums, and
-// with kh = 2 the waves' partial pixel sums (2 KB per wave)
+// dynamic LDS of a separable launch: per-trap coefficients (32 B) and weights (8 B), the tables of
+// sc traps for the block's 16 W columns and 16 rows (plain and weighted), W kh per-wave trap sums,
+// and with kh = 2 the waves' partial pixel sums (2 KB per wave)
 constexpr int kSepLdsMax = 160 * 1024 - 1024;
 inline size_t sep_lds_bytes(int W, int sc, int mmax, int kh = 1) {
   const size_t mp = (size_t)(mmax + 15) / 16 * 16;
-  return 24 * mp + 8 * (size_t)(sc + 2) * (16 * W + 32) + 8 * (size_t)W * kh * sc + (kh == 2 ? 2048 * (size_t)W * kh : 0);
+  return 40 * mp + 8 * (size_t)(sc + 2) * (16 * W + 32) + 8 * (size_t)W * kh * sc + (kh == 2 ? 2048 * (size_t)W * kh : 0);
 }
+
+// Micro-benchmarks (hot_probes.hip): issue-rate probe of kind 0 (FMA), 1 (sin/cos) or 2 (the
+// direct passes' term: 4 FMA + sin + cos); every wave writes {shader clock, shader clock,
+// real-time clock, real-time clock} at its start and end to stamps[4 wave .. 4 wave + 3].
+int probe_ops_per_rep(int kind);
+hipError_t launch_probe(hipStream_t s, int kind, int blocks, int threads, long long reps, float seed, float* sink,
+                        unsigned long long* stamps);
+// Device copy of n16 16-byte words on `blocks` blocks of 256 threads.
+hipError_t launch_probe_copy(hipStream_t s, const void* src, void* dst, size_t n16, int blocks);
 
 // 8-bit SLM frame encoding.
 hipError_t launch_encode_u8(hipStream_t s, const float* phase, uint8_t* frame, int64_t n);

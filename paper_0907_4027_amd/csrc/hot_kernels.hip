@@ -247,9 +247,10 @@ __device__ void update_traps(VGet vmem, const TrapState* __restrict__ st_in, int
   }
 }
 
-// Pixel-pass terms for Q pixels of one lane: S += w_m e^{i 2pi (g U^2 + a U + C_m)} over all
-// traps.  Per term: 2 FMA, sin, cos, 2 FMA.  The per-trap record {a, g, C_m, w_m} (C_m =
-// g V^2 + b V + theta_rev: everything constant along the row) is an LDS broadcast, and the
+// Pixel-pass terms for Q pixels of one lane: S += w_m e^{i 2pi (g u^2 + a' u + C_m)} over all
+// traps, u = U - Uc the lane's pixel relative to the block's reference (hot_internal.h).  Per
+// term: 2 FMA, sin, cos, 2 FMA.  The per-trap record {a', g, C_m, w_m} (C_m = K + theta_rev:
+// everything constant over the block's pixels) is an LDS broadcast, and the
 // records of the next kTrapChunk traps are loaded while the current ones are used.  Only LDS
 // loads are in flight here, so the in-order LDS counter lets the compiler wait for exactly
 // the records it needs (a scalar load in the loop would force a wait for all of them).
@@ -308,51 +309,64 @@ __device__ __forceinline__ void pixel_terms(const float4* rec, int M, const floa
   }
 }
 
-// Stage the pixel-pass records of one row: {a, g, g V^2 + b V + theta_rev, w}, zero-padded.
-template <int NT>
-__device__ __forceinline__ void stage_record(float4* rec, const TrapCoef& c, float Vr, float V2, float theta_rev,
-                                             float w, int m) {
-  rec[m] = make_float4(c.a, c.g, __builtin_fmaf(c.g, V2, __builtin_fmaf(c.b, Vr, theta_rev)), w);
+// The block reference of a trap (hot_internal.h): a' = a + 2 g Uc reduced mod 1/2 (u is even) and
+// K = g (Uc^2 + V^2) + a Uc + b V reduced mod 1, both in FP64 (exact to ~1e-16 rev: the products
+// of the coefficients with these integers are exact, each sum rounds once), then rounded to FP32.
+__device__ __forceinline__ float block_slope(const TrapCoef& c, double Uc) {
+  double ap = __builtin_fma(2.0 * c.g, Uc, c.a);
+  ap -= 0.5 * __builtin_rint(2.0 * ap);
+  return (float)ap;
+}
+__device__ __forceinline__ float block_const(const TrapCoef& c, double Uc, double V) {
+  const double k = __builtin_fma(c.g, __builtin_fma(Uc, Uc, V * V), __builtin_fma(c.a, Uc, c.b * V));
+  return (float)(k - __builtin_floor(k));
+}
+// Centre of a block's pixels [c0, c0 + len): Uc of the column c0 + (len - 1) / 2.
+__device__ __forceinline__ int centre_col(int c0, int len) { return c0 + (max(len, 1) - 1) / 2; }
+
+// Pixel-pass record of trap m: {a', g, K + theta_rev, w}; records past M are zero (w = 0).
+__device__ __forceinline__ void stage_record(float4* rec, int m, float ap, float gf, float k, float theta_rev,
+                                             float w) {
+  rec[m] = make_float4(ap, gf, k + theta_rev, w);
 }
 template <int NT>
 __device__ __forceinline__ void pad_records(float4* rec, int M) {
   for (int m = M + (int)threadIdx.x; m < rec_pad(M); m += NT) rec[m] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
 }
 
-// Trap pass over one row segment whose pixels (phi_rev, U, U^2, mask) sit in LDS `px`
-// (len real entries, zero-padded to S * slen).  Each wave is split into A slices of G
-// lanes; lane (slice s, position l) owns traps l, l+G, ..., l+(TPL-1)G of a chunk and
-// loops over the pixels of its slice:
-//   t = phi - a_m U - g_m U^2                2 VALU
+// Trap pass over one row segment whose pixels (phi_rev, u, u^2, mask) sit in LDS `px`
+// (len real entries, zero-padded to S * slen), u relative to the block's reference.  Each wave
+// is split into A slices of G lanes; lane (slice s, position l) owns traps l, l+G, ...,
+// l+(TPL-1)G of a chunk and loops over the pixels of its slice:
+//   t = phi - a'_m u - g_m u^2               2 VALU
 //   sin t, cos t                             2 transcendental
 //   acc += mask (cos t, sin t)              2 VALU
 // The S slice partials of each trap are then summed in slice order through LDS `red`.  The
-// row-constant part of Eq. 2, C_m = g V^2 + b V, is left out of the pixel sums: the sum of each
-// trap over a row is turned by e^{-i 2pi C_m} once, by the thread that sums its slices, and
-// handed to store(m, sum).
-// The coefficients one trap-pass lane needs for the traps it owns in one chunk: -a and -g.
-// Slots past M take trap M - 1's coefficients (always a valid read, and the arguments stay in
-// the sin/cos domain); their sums are never written out.  The loads are unconditional so that
-// the compiler need not wait for them where a conditional default would be merged in.
+// block constant K_m of Eq. 2 is left out of the pixel sums: the sum of each trap over a row is
+// turned by e^{-i 2pi K_m} once, by the thread that sums its slices, and handed to store(m, sum).
+// The lane coefficients of a chunk are -a' and -g of the traps the lane owns (the trap's K for
+// row h sits at kt[h * kt_stride + m]).  Slots past M take trap M - 1's coefficients (always a
+// valid read, and the arguments stay in the sin/cos domain); their sums are never written out.
 template <int TPL>
 struct LaneCoef {
   float na[TPL], ng[TPL];
 };
+// ... from the FP64 coefficients in global memory (a' formed here, as the records form it) ...
 template <int TPL>
-__device__ __forceinline__ LaneCoef<TPL> load_lane_coef(const TrapCoef* __restrict__ cf, int M, int G, int k0) {
+__device__ __forceinline__ LaneCoef<TPL> load_lane_coef(const TrapCoef* __restrict__ cf, int M, int G, int k0,
+                                                        double Uc) {
   const int lane = threadIdx.x & 63;
   const int tl = lane - lane / G * G;
   LaneCoef<TPL> lc;
 #pragma unroll
   for (int k = 0; k < TPL; ++k) {
     const TrapCoef c = cf[min(k0 + tl + k * G, M - 1)];
-    lc.na[k] = -c.a;
-    lc.ng[k] = -c.g;
+    lc.na[k] = -block_slope(c, Uc);
+    lc.ng[k] = -c.gf;
   }
   return lc;
 }
-
-// The same coefficients from the staged pixel-pass records {a, g, ., w} of the first chunk (k0 = 0).
+// ... or, for the first chunk, from the staged pixel-pass records {a', g, ., .} in LDS.
 template <int TPL>
 __device__ __forceinline__ LaneCoef<TPL> lane_coef_from_records(const float4* rec, int M, int G) {
   const int lane = threadIdx.x & 63;
@@ -367,16 +381,14 @@ __device__ __forceinline__ LaneCoef<TPL> lane_coef_from_records(const float4* re
   return lc;
 }
 
-// `first` holds the lane's coefficients of the first chunk (k0 = 0) and `cfirst` trap
-// min(threadIdx.x, M - 1)'s record, both read by the caller before its own global stores, so
-// that waiting for them does not wait for those stores too.
+// `first` holds the lane's coefficients of the first chunk (k0 = 0), read by the caller before
+// its own global stores, so that waiting for them does not wait for those stores too.
 // With ROWS = 2 the block is two halves of W waves, each passing over its own row (px and len of
-// the calling thread's half); Vb is the row coordinate V of the first half, Vb + 2 that of the
-// second.  store(m, sum) gets the block's sum over its rows.
+// the calling thread's half).  store(m, sum) gets the block's sum over its rows.
 template <int W, int TPL, bool FRACT, int ROWS, class Store>
-__device__ __forceinline__ void trap_pass_block(const TrapCoef* __restrict__ cf, int M, int G, int A, float Vb,
-                                                const float4* px, int len, float2* red, Store store,
-                                                const LaneCoef<TPL>& first, const TrapCoef& cfirst) {
+__device__ __forceinline__ void trap_pass_block(const TrapCoef* __restrict__ cf, double Uc, const float* kt,
+                                                int kt_stride, int M, int G, int A, const float4* px, int len,
+                                                float2* red, Store store, const LaneCoef<TPL>& first) {
   constexpr int NB = ROWS * W * 64;
   const int half = (int)threadIdx.x / (W * 64);
   const int wave = ((int)threadIdx.x >> 6) - half * W, lane = threadIdx.x & 63;
@@ -388,9 +400,7 @@ __device__ __forceinline__ void trap_pass_block(const TrapCoef* __restrict__ cf,
   const float4* mine = px + sidx * slen;
   const int nslot = G * TPL;
   for (int k0 = 0; k0 < M; k0 += nslot) {
-    const LaneCoef<TPL> lc = k0 == 0 ? first : load_lane_coef<TPL>(cf, M, G, k0);
-    // record of the trap this thread sums first after the pixels (read now, used after them)
-    const TrapCoef cm = k0 == 0 ? cfirst : cf[min(k0 + (int)threadIdx.x, M - 1)];
+    const LaneCoef<TPL> lc = k0 == 0 ? first : load_lane_coef<TPL>(cf, M, G, k0, Uc);
     float na[TPL], ng[TPL], accr[TPL], acci[TPL];
 #pragma unroll
     for (int k = 0; k < TPL; ++k) {
@@ -455,10 +465,10 @@ __device__ __forceinline__ void trap_pass_block(const TrapCoef* __restrict__ cf,
     for (int i = threadIdx.x; i < nslot; i += NB) {
       const int m = k0 + i;
       if (m < M) {
-        const TrapCoef c = i == (int)threadIdx.x ? cm : cf[m];
         float2 acc = make_float2(0.0f, 0.0f);
 #pragma unroll
         for (int h = 0; h < ROWS; ++h) {
+          const float kh = kt[h * kt_stride + m];
           // the slices in order; the reads go out in groups so that their latencies overlap
           const float2* rp = red + h * S * nslot + i;
           float sr = 0.0f, si = 0.0f;
@@ -488,10 +498,8 @@ __device__ __forceinline__ void trap_pass_block(const TrapCoef* __restrict__ cf,
             sr += rp[s2 * nslot].x;
             si += rp[s2 * nslot].y;
           }
-          const float vr = Vb + 2.0f * (float)h;
-          const float t = to_period<FRACT>(__builtin_fmaf(c.g, vr * vr, c.b * vr));
-          const float cs = __builtin_amdgcn_cosf(t), sn = __builtin_amdgcn_sinf(t);
-          acc.x += __builtin_fmaf(sr, cs, si * sn);  // (sr + i si) e^{-i 2pi t}
+          const float cs = __builtin_amdgcn_cosf(kh), sn = __builtin_amdgcn_sinf(kh);
+          acc.x += __builtin_fmaf(sr, cs, si * sn);  // (sr + i si) e^{-i 2pi K}
           acc.y += __builtin_fmaf(si, cs, -sr * sn);
         }
         store(m, acc);
@@ -534,6 +542,7 @@ k_iter(HoloDesc one, const TrapCoef* __restrict__ coef, const TrapState* __restr
   constexpr int UN = 2 * ROWS * RECN > REDN ? 2 * ROWS * RECN : REDN;  // in float2 units
   __shared__ float4 pxs[ROWS * PXN];
   __shared__ float2 ubuf[UN];  // pixel-pass records (one set per row), then slice partials
+  __shared__ float kts[ROWS * kMaxTraps];  // K of each trap and row (the trap pass's turn)
   __shared__ float sh[8 * NB / 64];
   const int b = blockIdx.z, sg = blockIdx.x;
   const int half = ROWS == 1 ? 0 : (int)threadIdx.x / NT, tid = (int)threadIdx.x - half * NT;
@@ -545,6 +554,10 @@ k_iter(HoloDesc one, const TrapCoef* __restrict__ coef, const TrapState* __restr
   float4* px = pxs + half * PXN;
   const bool lead = sg == 0 && blockIdx.y == 0;
   const VAcc vacc{acc_in, T, off, unscale};
+  // the block's reference column (the centre of its segment; the same for both rows)
+  const int cbeg = sg * seg_w;
+  const int cc = centre_col(cbeg, min(nx, cbeg + seg_w) - cbeg);
+  const double Uc = (double)(2 * cc - (nx - 1));
 
   // Every read of the block's own trap data is issued here, unconditionally (threads past M read
   // trap M - 1 and ignore it), so the update waits for one memory round trip.
@@ -559,12 +572,14 @@ k_iter(HoloDesc one, const TrapCoef* __restrict__ coef, const TrapState* __restr
     }
   }
   auto coef_of = [&](int m) { return m == (int)threadIdx.x ? c_first : cf[m]; };
-  // records of trap m for every row of the block
+  // records and K of trap m for every row of the block
   auto stage = [&](int m, const TrapCoef& c, const TrapState& s) {
+    const float ap = block_slope(c, Uc);
 #pragma unroll
     for (int h = 0; h < ROWS; ++h) {
-      const float vr = (float)(2 * (int)(blockIdx.y * ROWS + h) - (ny - 1));
-      stage_record<NT>(rec_all + h * RECN, c, vr, vr * vr, s.theta_rev, s.w, m);
+      const float k = block_const(c, Uc, (double)(2 * (int)(blockIdx.y * ROWS + h) - (ny - 1)));
+      stage_record(rec_all + h * RECN, m, ap, c.gf, k, s.theta_rev, s.w);
+      kts[h * kMaxTraps + m] = k;
     }
   };
   if (upd == 0) {
@@ -582,17 +597,16 @@ k_iter(HoloDesc one, const TrapCoef* __restrict__ coef, const TrapState* __restr
   for (int h = 0; h < ROWS; ++h) pad_records<NB>(rec_all + h * RECN, M);
   __syncthreads();
 
-  const int cbeg = sg * seg_w;
   const int len = r < ny ? min(nx, cbeg + seg_w) - cbeg : 0;  // a missing last row has no pixels
-  float U[Q], U2[Q], sr[Q], si[Q];
+  float u[Q], u2[Q], sr[Q], si[Q];
 #pragma unroll
   for (int q = 0; q < Q; ++q) {
-    U[q] = (float)(2 * (cbeg + tid + q * NT) - (nx - 1));
-    U2[q] = U[q] * U[q];
+    u[q] = (float)(2 * (cbeg + tid + q * NT - cc));
+    u2[q] = u[q] * u[q];
     sr[q] = 0.0f;
     si[q] = 0.0f;
   }
-  pixel_terms<Q, FRACT>(rec_all + half * RECN, M, U, U2, sr, si);
+  pixel_terms<Q, FRACT>(rec_all + half * RECN, M, u, u2, sr, si);
   // the trap pass's first-chunk coefficients, from the records while they are still in LDS
   const LaneCoef<TPL> lane_first = lane_coef_from_records<TPL>(rec_all, M, G);
   float* __restrict__ prow = phase + (size_t)b * nx * ny + (size_t)r * nx + cbeg;
@@ -602,7 +616,7 @@ k_iter(HoloDesc one, const TrapCoef* __restrict__ coef, const TrapState* __restr
     if (i < len) {
       const float ph = phase_of(si[q], sr[q]);
       prow[i] = ph;
-      px[i] = make_float4(ph * kInv2Pi, U[q], U2[q], 1.0f);
+      px[i] = make_float4(ph * kInv2Pi, u[q], u2[q], 1.0f);
     } else {
       px[i] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
     }
@@ -613,8 +627,7 @@ k_iter(HoloDesc one, const TrapCoef* __restrict__ coef, const TrapState* __restr
   auto add_sum = [&](int m, float2 v) {
     __hip_atomic_fetch_add(mine + m, pack_sum(v, scale), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   };
-  trap_pass_block<W, TPL, FRACT, ROWS>(cf, M, G, A, (float)(2 * (int)(blockIdx.y * ROWS) - (ny - 1)), px, len,
-                                       ubuf, add_sum, lane_first, c_first);
+  trap_pass_block<W, TPL, FRACT, ROWS>(cf, Uc, kts, kMaxTraps, M, G, A, px, len, ubuf, add_sum, lane_first);
 }
 
 // ------------------------------------------------------------------ stand-alone passes
@@ -631,8 +644,10 @@ k_backward(const TrapCoef* __restrict__ coef, const TrapState* __restrict__ st, 
   const int b = blockIdx.z, r = blockIdx.y;
   const int M = hd[b].m, off = hd[b].off;
   const TrapCoef* __restrict__ cf = coef + off;
-  const float Vr = (float)(2 * r - (ny - 1));
-  const float V2 = Vr * Vr;
+  // the block's pixels: columns [c0, c0 + kBlock Q) of row r, referenced to their centre
+  const int c0 = blockIdx.x * (kBlock * Q);
+  const int cc = centre_col(c0, min(nx, c0 + kBlock * Q) - c0);
+  const double Uc = (double)(2 * cc - (nx - 1)), Vr = (double)(2 * r - (ny - 1));
   for (int m = threadIdx.x; m < M; m += kBlock) {
     float th, w;
     if constexpr (MODE == 0) {
@@ -644,20 +659,21 @@ k_backward(const TrapCoef* __restrict__ coef, const TrapState* __restrict__ st, 
       w = sqrtf(gr * gr + gi * gi);
       th = atan2f(gi, gr) * kInv2Pi;
     }
-    stage_record<kBlock>(rec, cf[m], Vr, V2, th, w, m);
+    const TrapCoef c = cf[m];
+    stage_record(rec, m, block_slope(c, Uc), c.gf, block_const(c, Uc, Vr), th, w);
   }
   pad_records<kBlock>(rec, M);
   __syncthreads();
-  const int cbase = blockIdx.x * (kBlock * Q) + threadIdx.x;
-  float U[Q], U2[Q], sr[Q], si[Q];
+  const int cbase = c0 + threadIdx.x;
+  float u[Q], u2[Q], sr[Q], si[Q];
 #pragma unroll
   for (int q = 0; q < Q; ++q) {
-    U[q] = (float)(2 * (cbase + q * kBlock) - (nx - 1));
-    U2[q] = U[q] * U[q];
+    u[q] = (float)(2 * (cbase + q * kBlock - cc));
+    u2[q] = u[q] * u[q];
     sr[q] = 0.0f;
     si[q] = 0.0f;
   }
-  pixel_terms<Q, FRACT>(rec, M, U, U2, sr, si);
+  pixel_terms<Q, FRACT>(rec, M, u, u2, sr, si);
   const size_t rowbase = (size_t)b * nx * ny + (size_t)r * nx;
 #pragma unroll
   for (int q = 0; q < Q; ++q) {
@@ -682,20 +698,24 @@ k_forward(const TrapCoef* __restrict__ coef, const HoloDesc* __restrict__ hd, co
   constexpr int W = kBlock / 64;
   __shared__ float4 px[kSegMax + 72];  // slices cover < len + S <= len + 64 entries, plus 3 read ahead
   __shared__ float2 red[W * 64 * TPL];
+  __shared__ float kt[kMaxTraps];
   const int b = blockIdx.z, r = blockIdx.y, sg = blockIdx.x;
   const int M = hd[b].m, G = hd[b].g, A = hd[b].a, off = hd[b].off;
+  const TrapCoef* __restrict__ cf = coef + off;
   const int cbeg = sg * seg_w;
   const int len = min(nx, cbeg + seg_w) - cbeg;
+  const int cc = centre_col(cbeg, len);
+  const double Uc = (double)(2 * cc - (nx - 1)), Vr = (double)(2 * r - (ny - 1));
   const int S = W * A;
   const int padded = S * ((len + S - 1) / S) + 4;  // zeros past the last slice for the read-ahead
   const float* __restrict__ ph = phase + (size_t)b * nx * ny + (size_t)r * nx + cbeg;
-  const float Vr = (float)(2 * r - (ny - 1));
-  const LaneCoef<TPL> lane_first = load_lane_coef<TPL>(coef + off, M, G, 0);
-  const TrapCoef c_first = coef[off + min((int)threadIdx.x, M - 1)];
+  const LaneCoef<TPL> lane_first = load_lane_coef<TPL>(cf, M, G, 0, Uc);
+  for (int m = threadIdx.x; m < M; m += kBlock) kt[m] = block_const(cf[m], Uc, Vr);
   for (int i = threadIdx.x; i < padded; i += kBlock) {
     if (i < len) {
-      const float U = (float)(2 * (cbeg + i) - (nx - 1));
-      px[i] = make_float4(ph[i] * kInv2Pi, U, U * U, 1.0f);
+      const float u = (float)(2 * (cbeg + i - cc));
+      // any phase the caller passes, wrapped to one period (exact)
+      px[i] = make_float4(__builtin_amdgcn_fractf(ph[i] * kInv2Pi), u, u * u, 1.0f);
     } else {
       px[i] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
     }
@@ -703,8 +723,8 @@ k_forward(const TrapCoef* __restrict__ coef, const HoloDesc* __restrict__ hd, co
   __syncthreads();
   const int nblk = ny * nseg;
   float2* __restrict__ out = partial + (size_t)off * nblk + r * nseg + sg;
-  trap_pass_block<W, TPL, FRACT, 1>(coef + off, M, G, A, Vr, px, len, red,
-                                    [&](int m, float2 v) { out[(size_t)m * nblk] = v; }, lane_first, c_first);
+  trap_pass_block<W, TPL, FRACT, 1>(cf, Uc, kt, 0, M, G, A, px, len, red,
+                                    [&](int m, float2 v) { out[(size_t)m * nblk] = v; }, lane_first);
 }
 
 // ------------------------------------------------------------------ reduce, update, finalize
@@ -778,7 +798,8 @@ k_update(const float* __restrict__ V, const HoloDesc* __restrict__ hd, const Tra
 
 // ------------------------------------------------------------------ stored exp(i Delta) variant
 
-template <bool FRACT>
+// A[m][j] = exp(i 2pi Delta_rev): the argument is formed exactly in FP64 and reduced to one period
+// before the FP32 sin/cos (a one-time table, so the FP64 work is cheap).
 __global__ void __launch_bounds__(kBlock)
 k_expdelta(const TrapCoef* __restrict__ coef, const HoloDesc* __restrict__ hd, int nx, int ny, float2* __restrict__ A) {
   const int b = blockIdx.z, m = blockIdx.y;
@@ -789,9 +810,9 @@ k_expdelta(const TrapCoef* __restrict__ coef, const HoloDesc* __restrict__ hd, i
   float2* __restrict__ row = A + (size_t)(off + m) * n;
   for (int j = blockIdx.x * kBlock + threadIdx.x; j < n; j += gridDim.x * kBlock) {
     const int r = j / nx, col = j - r * nx;
-    const float U = (float)(2 * col - (nx - 1)), Vr = (float)(2 * r - (ny - 1));
-    const float t = to_period<FRACT>(
-        __builtin_fmaf(c.g, U * U, __builtin_fmaf(c.a, U, __builtin_fmaf(c.g, Vr * Vr, __builtin_fmaf(c.b, Vr, 0.0f)))));
+    const double U = (double)(2 * col - (nx - 1)), Vr = (double)(2 * r - (ny - 1));
+    const double d = __builtin_fma(c.g, __builtin_fma(U, U, Vr * Vr), __builtin_fma(c.a, U, c.b * Vr));
+    const float t = (float)(d - __builtin_floor(d));
     row[j] = make_float2(__builtin_amdgcn_cosf(t), __builtin_amdgcn_sinf(t));
   }
 }
@@ -805,7 +826,8 @@ k_backward_stored(const float2* __restrict__ A, const TrapState* __restrict__ st
   const int M = hd[b].m, off = hd[b].off;
   for (int m = threadIdx.x; m < M; m += kBlock) {
     const TrapState s = st[off + m];
-    cm[m] = make_float2(s.w * __builtin_amdgcn_cosf(s.theta_rev), s.w * __builtin_amdgcn_sinf(s.theta_rev));
+    const float t = __builtin_amdgcn_fractf(s.theta_rev);
+    cm[m] = make_float2(s.w * __builtin_amdgcn_cosf(t), s.w * __builtin_amdgcn_sinf(t));
   }
   __syncthreads();
   const int j = blockIdx.x * kBlock + threadIdx.x;
@@ -1019,7 +1041,7 @@ __device__ __forceinline__ void trap_tiles(const float2* xc, const float2* yc, i
 //   written by the first.  Twice the waves per SIMD, the same work.
 // Grid (ceil(nx / 16 W), ceil(ny / 16), B), W KH waves per block; sc = traps per super-chunk (a
 // multiple of 16); dynamic LDS sep_lds_bytes(W, sc, Mmax, KH).
-template <int W, int MODE, bool FRACT, int KH>
+template <int W, int MODE, int KH>
 __global__ void __launch_bounds__(W * KH * 64)
 k_sep(const TrapCoef* __restrict__ coef, const HoloDesc* __restrict__ hd, const TrapState* __restrict__ st_in,
       TrapState* __restrict__ st_out, const float* __restrict__ vin, float* __restrict__ stats, int kstat,
@@ -1036,7 +1058,7 @@ k_sep(const TrapCoef* __restrict__ coef, const HoloDesc* __restrict__ hd, const 
   const int M = hd[b].m, off = hd[b].off;
   const int Mp = (M + 15) & ~15;
   const int XS = sc + 2;  // row stride of the table copies (float2), skewed across banks
-  float4* cf = lds4;                                     // [Mp] {a, g, b, 0}
+  TrapCoef* cf = reinterpret_cast<TrapCoef*>(lds4);     // [Mp] FP64 coefficients
   float2* cw = reinterpret_cast<float2*>(cf + Mp);       // [Mp] c_m
   float2* xt = cw + Mp;                                  // [CW][XS] X_m(c)
   float2* yt = xt + CW * XS;                             // [16][XS] Y_m(r)
@@ -1057,40 +1079,35 @@ k_sep(const TrapCoef* __restrict__ coef, const HoloDesc* __restrict__ hd, const 
 
   // tables of traps [k0, k0 + n) into LDS: lane j keeps trap k0 + j's coefficients in registers
   // while its wave walks the block's columns wave, wave + NW, ... (tables_x) or rows wave,
-  // wave + NW, ... (tables_y).  Columns past nx and rows past ny take the coordinates of the last column
-  // and row (finite entries inside the sin/cos domain; such pixels have E = 0), and traps past M
-  // are left as the formula gives them (c_m = 0, partials never written), so none of them reach
-  // V or the phase.
+  // wave + NW, ... (tables_y).  Each argument, g U^2 + a U or g V^2 + b V, is formed in FP64
+  // (exact to ~1e-16 rev for these integer U, V) and reduced to one period before the FP32
+  // sin/cos.  Columns past nx and rows past ny take the coordinates of the last column and row
+  // (finite entries; such pixels have E = 0), and traps past M are left as the formula gives
+  // them (c_m = 0, partials never written), so none of them reach V or the phase.
   static_assert(16 % NW == 0, "rows of a block split evenly over its waves");
-  float xu[16 / KH], xu2[16 / KH], yv[16 / NW], yv2[16 / NW];
-#pragma unroll
-  for (int i = 0; i < 16 / KH; ++i) {
-    xu[i] = (float)(2 * min(cb + wave + i * NW, nx - 1) - (nx - 1));
-    xu2[i] = xu[i] * xu[i];
-  }
-#pragma unroll
-  for (int i = 0; i < 16 / NW; ++i) {
-    yv[i] = (float)(2 * min(row0 + wave + i * NW, ny - 1) - (ny - 1));
-    yv2[i] = yv[i] * yv[i];
-  }
+  auto factor = [](double g, double lin, double X) {
+    const double d = __builtin_fma(g, X * X, lin * X);
+    const float t = (float)(d - __builtin_floor(d));
+    return make_float2(__builtin_amdgcn_cosf(t), __builtin_amdgcn_sinf(t));
+  };
   auto tables_x = [&](int k0, int n) {
     for (int j = lane; j < n; j += 64) {
-      const float4 k = cf[k0 + j];
+      const TrapCoef k = cf[k0 + j];
 #pragma unroll
       for (int i = 0; i < 16 / KH; ++i) {
-        const float t = to_period<FRACT>(__builtin_fmaf(k.y, xu2[i], k.x * xu[i]));
-        xt[(wave + i * NW) * XS + j] = make_float2(__builtin_amdgcn_cosf(t), __builtin_amdgcn_sinf(t));
+        const double U = (double)(2 * min(cb + wave + i * NW, nx - 1) - (nx - 1));
+        xt[(wave + i * NW) * XS + j] = factor(k.g, k.a, U);
       }
     }
   };
   auto tables_y = [&](int k0, int n, bool weighted) {
     for (int j = lane; j < n; j += 64) {
-      const float4 k = cf[k0 + j];
+      const TrapCoef k = cf[k0 + j];
       const float2 w = weighted ? cw[k0 + j] : make_float2(0.0f, 0.0f);
 #pragma unroll
       for (int i = 0; i < 16 / NW; ++i) {
-        const float t = to_period<FRACT>(__builtin_fmaf(k.y, yv2[i], k.z * yv[i]));
-        const float2 v = make_float2(__builtin_amdgcn_cosf(t), __builtin_amdgcn_sinf(t));
+        const double V = (double)(2 * min(row0 + wave + i * NW, ny - 1) - (ny - 1));
+        const float2 v = factor(k.g, k.b, V);
         yt[(wave + i * NW) * XS + j] = v;
         if (weighted) ywt[(wave + i * NW) * XS + j] = cmul(w, v);
       }
@@ -1103,7 +1120,7 @@ k_sep(const TrapCoef* __restrict__ coef, const HoloDesc* __restrict__ hd, const 
   // the update's inputs arrive, and only then does the GS/GSW update.
   const VAcc vacc{acc_in, T, off, unscale};
   const bool lead = blockIdx.x == 0 && blockIdx.y == 0;
-  TrapCoef c_first = {0.0f, 0.0f, 0.0f, 0.0f};
+  TrapCoef c_first = {0.0, 0.0, 0.0, 0.0f, 0.0f};
   float2 v_first = make_float2(0.0f, 0.0f);
   TrapState s_first = {0.0f, 0.0f, 0.0f, 0.0f};
   if ((int)threadIdx.x < M) {
@@ -1119,15 +1136,8 @@ k_sep(const TrapCoef* __restrict__ coef, const HoloDesc* __restrict__ hd, const 
       acc_zero[(size_t)gi * T + off + (i - gi * M)] = 0ull;
     }
   }
-  for (int m = NT + (int)threadIdx.x; m < Mp; m += NT) {
-    float4 v = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-    if (m < M) {
-      const TrapCoef c = coef[off + m];
-      v = make_float4(c.a, c.g, c.b, 0.0f);
-    }
-    cf[m] = v;
-  }
-  if ((int)threadIdx.x < Mp) cf[threadIdx.x] = make_float4(c_first.a, c_first.g, c_first.b, 0.0f);
+  for (int m = NT + (int)threadIdx.x; m < Mp; m += NT) cf[m] = m < M ? coef[off + m] : TrapCoef{0.0, 0.0, 0.0, 0.0f, 0.0f};
+  if ((int)threadIdx.x < Mp) cf[threadIdx.x] = c_first;
   __syncthreads();
   if constexpr (kPixel) {
     tables_x(0, min(sc, Mp));
@@ -1214,7 +1224,7 @@ k_sep(const TrapCoef* __restrict__ coef, const HoloDesc* __restrict__ hd, const 
     for (int v = 0; v < 4; ++v) {
       if constexpr (MODE == 3) {
         if (in[v]) {
-          const float pr = phase[pix0 + v] * kInv2Pi;
+          const float pr = __builtin_amdgcn_fractf(phase[pix0 + v] * kInv2Pi);
           grad[pix0 + v] =
               inv_n * (__builtin_amdgcn_cosf(pr) * sim[v] - __builtin_amdgcn_sinf(pr) * sre[v]);  // Im(e^{-i phi} S)
         }
@@ -1238,7 +1248,7 @@ k_sep(const TrapCoef* __restrict__ coef, const HoloDesc* __restrict__ hd, const 
   } else {
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
-      const float pr = in[v] ? phase[pix0 + v] * kInv2Pi : 0.0f;
+      const float pr = in[v] ? __builtin_amdgcn_fractf(phase[pix0 + v] * kInv2Pi) : 0.0f;
       er[v] = in[v] ? __builtin_amdgcn_cosf(pr) : 0.0f;
       ei[v] = in[v] ? __builtin_amdgcn_sinf(pr) : 0.0f;
     }
@@ -1387,7 +1397,7 @@ hipError_t backward_sel(hipStream_t s, int q, int nx, int ny, int B, const TrapC
   switch (q) {
     case 1: return backward_q<1, FRACT, MODE>(s, nx, ny, B, coef, st, hd, phase, G, grad, inv_n);
     case 2: return backward_q<2, FRACT, MODE>(s, nx, ny, B, coef, st, hd, phase, G, grad, inv_n);
-    default: return backward_q<4, FRACT, MODE>(s, nx, ny, B, coef, st, hd, phase, G, grad, inv_n);
+    default: return hipErrorInvalidValue;
   }
 }
 
@@ -1462,14 +1472,11 @@ hipError_t launch_update(hipStream_t s, int B, const float* V, const HoloDesc* h
   return hipGetLastError();
 }
 
-hipError_t launch_expdelta(hipStream_t s, int nx, int ny, int B, int mmax, bool fract, const TrapCoef* coef,
+hipError_t launch_expdelta(hipStream_t s, int nx, int ny, int B, int mmax, const TrapCoef* coef,
                            const HoloDesc* hd, float2* A) {
   const int n = nx * ny;
   dim3 grid(std::min((n + kBlock - 1) / kBlock, 1024), mmax, B);
-  if (fract)
-    hipLaunchKernelGGL(k_expdelta<true>, grid, dim3(kBlock), 0, s, coef, hd, nx, ny, A);
-  else
-    hipLaunchKernelGGL(k_expdelta<false>, grid, dim3(kBlock), 0, s, coef, hd, nx, ny, A);
+  hipLaunchKernelGGL(k_expdelta, grid, dim3(kBlock), 0, s, coef, hd, nx, ny, A);
   return hipGetLastError();
 }
 
@@ -1490,36 +1497,31 @@ hipError_t launch_forward_stored(hipStream_t s, int n, int B, int mmax, const fl
   return hipGetLastError();
 }
 
-template <int W, int MODE, bool FRACT, int KH>
+template <int W, int MODE, int KH>
 hipError_t sep_t(hipStream_t s, const SepArgs& a) {
   // raise the kernel's dynamic LDS limit once, to everything the static part leaves
-  static const hipError_t attr = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_sep<W, MODE, FRACT, KH>),
+  static const hipError_t attr = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_sep<W, MODE, KH>),
                                                      hipFuncAttributeMaxDynamicSharedMemorySize, kSepLdsMax);
   if (attr != hipSuccess) return attr;
   const size_t lds = sep_lds_bytes(W, a.sc, a.mmax, KH);
   if (lds > (size_t)kSepLdsMax) return hipErrorInvalidValue;
   dim3 grid(a.gx(), a.gy(), a.B);
   if (MODE == 0 && (!a.acc_in || !a.acc_out || !a.acc_zero || a.T < 1)) return hipErrorInvalidValue;
-  hipLaunchKernelGGL((k_sep<W, MODE, FRACT, KH>), grid, dim3(W * KH * 64), lds, s, a.coef, a.hd, a.st_in, a.st_out,
+  hipLaunchKernelGGL((k_sep<W, MODE, KH>), grid, dim3(W * KH * 64), lds, s, a.coef, a.hd, a.st_in, a.st_out,
                      a.vin, a.stats, a.kstat, a.stat_stride, a.upd, a.flag, a.nx, a.ny, a.inv_n, a.sc, a.phase,
                      a.grad, a.partial, a.acc_in, a.acc_out, a.acc_zero, a.T, a.acc_scale, a.acc_unscale);
   return hipGetLastError();
 }
 
-template <int W, bool FRACT>
+template <int W>
 hipError_t sep_mode(hipStream_t s, const SepArgs& a) {
   switch (a.mode) {
-    case 0: return a.kh == 2 ? sep_t<W, 0, FRACT, 2>(s, a) : sep_t<W, 0, FRACT, 1>(s, a);
-    case 1: return sep_t<W, 1, FRACT, 1>(s, a);
-    case 2: return sep_t<W, 2, FRACT, 1>(s, a);
-    case 3: return sep_t<W, 3, FRACT, 1>(s, a);
+    case 0: return a.kh == 2 ? sep_t<W, 0, 2>(s, a) : sep_t<W, 0, 1>(s, a);
+    case 1: return sep_t<W, 1, 1>(s, a);
+    case 2: return sep_t<W, 2, 1>(s, a);
+    case 3: return sep_t<W, 3, 1>(s, a);
     default: return hipErrorInvalidValue;
   }
-}
-
-template <int W>
-hipError_t sep_fract(hipStream_t s, const SepArgs& a) {
-  return a.fract ? sep_mode<W, true>(s, a) : sep_mode<W, false>(s, a);
 }
 
 hipError_t launch_sep(hipStream_t s, const SepArgs& a) {
@@ -1528,9 +1530,9 @@ hipError_t launch_sep(hipStream_t s, const SepArgs& a) {
   if (a.nx < 1 || a.ny < 1 || a.mmax < 1 || a.mmax > kMaxTraps || a.sc < 16 || a.sc % 16 != 0)
     return hipErrorInvalidValue;
   switch (a.W) {
-    case 1: return sep_fract<1>(s, a);
-    case 2: return sep_fract<2>(s, a);
-    default: return sep_fract<4>(s, a);
+    case 1: return sep_mode<1>(s, a);
+    case 2: return sep_mode<2>(s, a);
+    default: return sep_mode<4>(s, a);
   }
 }
 

@@ -88,12 +88,13 @@ class Context:
 
     def set_tuning(self, pixels_per_lane: int = 0, traps_per_lane: int = 0, segment: int = 0,
                    slices: int = 0, sep_waves: int = 0, sep_chunk: int = 0, rows: int = 0,
-                   sep_split: int = 0) -> None:
+                   sep_split: int = 0, fract: int = 0) -> None:
         """Launch-shape knobs (0 = built-in choice); see hot_set_tuning in include/hot.h."""
         for key, val in ((_lib.HOT_TUNE_PIXELS_PER_LANE, pixels_per_lane), (_lib.HOT_TUNE_TRAPS_PER_LANE, traps_per_lane),
                          (_lib.HOT_TUNE_SEGMENT, segment), (_lib.HOT_TUNE_SLICES, slices),
                          (_lib.HOT_TUNE_SEP_WAVES, sep_waves), (_lib.HOT_TUNE_SEP_CHUNK, sep_chunk),
-                         (_lib.HOT_TUNE_ROWS, rows), (_lib.HOT_TUNE_SEP_SPLIT, sep_split)):
+                         (_lib.HOT_TUNE_ROWS, rows), (_lib.HOT_TUNE_SEP_SPLIT, sep_split),
+                         (_lib.HOT_TUNE_FRACT, fract)):
             check(self._lib, self._lib.hot_set_tuning(self._ctx, key, int(val)))
 
     def set_graphs(self, enabled: bool) -> None:
@@ -216,6 +217,24 @@ class Context:
         check(self._lib, self._lib.hot_time_passes(self._ctx, C.byref(s), M, _dp(x), _dp(th), int(reps),
                                                    _vp(phase), _vp(V), ms))
         return np.array(ms[:], dtype=np.float64)
+
+    def hot_probe_issue(self, kind: int, waves_per_simd: int, reps: int) -> dict:
+        """Issue-rate micro-benchmark (kind 0 FMA, 1 sin/cos, 2 the direct passes' term); see
+        include/hot.h.  Returns rates per second, the waves' mean shader clock and timings."""
+        out = (C.c_double * 6)()
+        check(self._lib, self._lib.hot_probe_issue(self._ctx, int(kind), int(waves_per_simd), int(reps), out))
+        return {"ops_per_s": out[0], "clock_hz": out[1], "span_s": out[2], "event_s": out[3],
+                "cycles_per_wave": out[4], "waves": int(out[5])}
+
+    def hot_probe_copy(self, src: torch.Tensor, dst: torch.Tensor, reps: int = 20) -> dict:
+        """Device copy bandwidth (bytes read + written per second) with the library's copy kernel."""
+        if not (src.is_cuda and dst.is_cuda and src.is_contiguous() and dst.is_contiguous()
+                and src.numel() * src.element_size() == dst.numel() * dst.element_size()):
+            raise ValueError("src and dst must be contiguous device tensors of the same byte size")
+        out = (C.c_double * 2)()
+        nbytes = src.numel() * src.element_size()
+        check(self._lib, self._lib.hot_probe_copy(self._ctx, _vp(src), _vp(dst), int(nbytes), int(reps), out))
+        return {"bytes_per_s": out[0], "ms_per_copy": out[1]}
 
     def hot_adjoint(self, slm, counts, xyz, phase: torch.Tensor, G: torch.Tensor, grad=None) -> torch.Tensor:
         s = as_slm(slm)

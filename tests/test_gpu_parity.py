@@ -13,7 +13,8 @@ import torch
 
 import oracle
 import workloads as W
-from tests.parity import as_complex, assert_phase, assert_stats, assert_V, to_np, wrapped_diff
+from tests.parity import (as_complex, assert_phase, assert_phase_within_conditioning, assert_stats, assert_V, to_np,
+                          wrapped_diff)
 
 pytestmark = pytest.mark.gpu
 
@@ -82,11 +83,14 @@ def test_matches_oracle_small(ctx, name, algo):
     g = run(ctx, algo, p, K)
     o = oracle.solve(algo, p.slm, p.xyz, p.theta0, K)
     if name == "odd-129x65-130" and algo == "gsw":
-        # 130 traps on 8385 pixels: many near-zero |S_j| (phase vortices), and six GSW
-        # iterations amplify FP32-vs-FP64 differences at them; single passes (rs) meet
-        # the 99.9 % bar on the same grid
-        assert_phase(to_np(g.phase), o["phi"], frac=0.995)
-        assert_V(to_np(g.V), o["V"], rtol=3e-4)
+        # 130 traps on 8385 pixels: the six-iteration GSW map amplifies rounding about a
+        # thousandfold here (in FP64 alone, theta0 moved by 1e-6 rad, the size of one FP32 pass's
+        # rms phase error, leaves only 99.8 % of pixels within 1e-3 rad), so the trajectory is held
+        # to that perturbed FP64 run; each single pass of it meets the usual bar on identical
+        # inputs (test_gpu_configs.py::test_odd_grid_130_traps_every_iteration)
+        pert = oracle.solve(algo, p.slm, p.xyz, p.theta0 + 1e-6 * np.random.default_rng(1).standard_normal(p.m), K)
+        assert_phase_within_conditioning(to_np(g.phase), o["phi"], pert["phi"])
+        assert_V(to_np(g.V), o["V"])
         assert_stats(g.stats, o["stats"])
         return
     if p.slm.n >= 64:
@@ -124,15 +128,15 @@ def test_512sq_100_traps_50_iterations(ctx, algo):
 
 def test_1024sq_256_traps_sampled(ctx):
     """40 GSW iterations at 1024^2 x 256: the final trap pass is checked in full (oracle Eq. 1 on the
-    GPU mask), the final pixel pass on 4096 sampled pixels (oracle Eq. 3 with the GPU's w, theta),
+    GPU mask), the final pixel pass on 65536 sampled pixels (oracle Eq. 3 with the GPU's w, theta),
     and a 3-iteration trajectory in full."""
     p = W.c3()
     g = run(ctx, "gsw", p, state=True)
     phi = to_np(g.phase).ravel()
     assert_V(to_np(g.V), oracle.forward(p.slm, p.xyz, phi), what="trap pass at K=40")
-    idx = np.random.default_rng(7).choice(p.slm.n, 4096, replace=False)
+    idx = np.random.default_rng(7).choice(p.slm.n, 65536, replace=False)
     ref = oracle.backward(p.slm, p.xyz, to_np(g.w), to_np(g.theta).astype(np.float64), idx=idx)
-    assert_phase(phi[idx], ref, frac=0.998, what="pixel pass at K=40")
+    assert_phase(phi[idx], ref, what="pixel pass at K=40")
     assert g.stats[-1, 1] > 0.9
     g3 = run(ctx, "gsw", p, 3)
     o3 = oracle.solve("gsw", p.slm, p.xyz, p.theta0, 3)
@@ -356,9 +360,10 @@ def test_seeded_theta_matches_splitmix(ctx):
 
 
 @pytest.mark.parametrize("variant", ["onthefly", "separable", "stored"])
-def test_large_phase_range_uses_explicit_reduction(hot, variant):
-    """Traps 0.4-0.6 mm off axis push |Delta| past the hardware sin/cos domain (256 rev): the
-    explicit fract() path of each kernel family must keep parity."""
+def test_off_axis_traps(hot, variant):
+    """Traps 0.4-0.6 mm off axis (beyond the SLM's field, so they alias): grating coefficients of
+    up to 0.85 revolutions per pixel-index unit, which the library reduces modulo one (exact, as the
+    pixel coordinates are integers) before any FP32 rounding; parity at the usual bar."""
     rng = np.random.default_rng(370)
     xyz = np.column_stack([rng.uniform(4e-4, 6e-4, 6), rng.uniform(-6e-4, -4e-4, 6), rng.uniform(-1e-5, 1e-5, 6)])
     p = W.Problem(W.Slm(256, 256), xyz, rng.uniform(0, 2 * math.pi, 6), 4)
@@ -366,8 +371,43 @@ def test_large_phase_range_uses_explicit_reduction(hot, variant):
         ctx.set_variant(variant)
         g = run(ctx, "gsw", p)
     o = oracle.solve("gsw", p.slm, p.xyz, p.theta0, p.iters)
-    assert_phase(to_np(g.phase), o["phi"], tol=3e-3)
-    assert_V(to_np(g.V), o["V"], rtol=3e-4)
+    assert_phase(to_np(g.phase), o["phi"])
+    assert_V(to_np(g.V), o["V"])
+
+
+@pytest.mark.parametrize("algo", ["rs", "gsw"])
+def test_forced_explicit_reduction(hot, algo):
+    """The explicit per-term reduction of the direct passes (fract, exact in FP32), switched on for
+    an ordinary problem: the usual bar (the reduction changes no result beyond rounding)."""
+    p = W.random_problem(372, 300, 140, 45, 5)
+    with hot.Context(0) as c:
+        c.set_tuning(fract=1)
+        g = run(c, algo, p)
+        V = to_np(c.hot_forward_V(p.slm, [p.m], p.xyz, g.phase.reshape(1, p.slm.ny, p.slm.nx)))
+        torch.cuda.synchronize()
+    o = oracle_solve(algo, p, p.iters)
+    assert_phase(to_np(g.phase), o["phi"])
+    assert_V(to_np(g.V), o["V"])
+    assert_V(V, oracle.forward(p.slm, p.xyz, to_np(g.phase).ravel()), what="Eq. 1 alone")
+
+
+def test_strong_defocus_takes_the_explicit_reduction(hot):
+    """Traps 3 mm out of focus: lens terms of up to ~200 revolutions per block, past the margin of
+    the hardware sin/cos domain, so the library reduces every argument explicitly.  A per-term
+    argument of up to 256 rev carries up to 1 ulp = 1.5e-5 rev (1e-4 rad) of FP32 rounding, so the
+    mask's error is at most 1e-4 sum(w) / |S_j| rad: the bar is 1e-3 rad on every pixel with
+    |S_j| >= sum(w) / 10 (identical inputs: the random-superposition pass), and |V| within 1e-4."""
+    rng = np.random.default_rng(373)
+    xyz = np.column_stack([rng.uniform(-2e-5, 2e-5, 6), rng.uniform(-2e-5, 2e-5, 6), rng.uniform(2.5e-3, 3e-3, 6)])
+    p = W.Problem(W.Slm(256, 256), xyz, rng.uniform(0, 2 * math.pi, 6), 0)
+    with hot.Context(0) as c:
+        g = run(c, "rs", p)
+    phi_ref, S = oracle.backward(p.slm, p.xyz, None, p.theta0, return_field=True)
+    ok = np.abs(S) >= p.m / 10
+    assert ok.mean() > 0.8
+    d = wrapped_diff(to_np(g.phase).ravel()[ok], phi_ref[ok])
+    assert d.max() <= 1e-3, d.max()
+    assert_V(to_np(g.V), oracle.forward(p.slm, p.xyz, to_np(g.phase).ravel()))
 
 
 @pytest.mark.parametrize("algo", ["rs", "gsw"])
@@ -380,6 +420,31 @@ def test_max_traps(ctx, algo):
     o = oracle.solve(algo, p.slm, p.xyz, p.theta0, 2)
     assert_phase(to_np(g.phase), o["phi"])
     assert_V(to_np(g.V), o["V"])
+
+
+@pytest.mark.parametrize("algo", ["rs", "gsw"])
+def test_max_traps_random_3d(ctx, algo):
+    """HOT_MAX_TRAPS random 3D traps in the 40 x 40 x 20 um box on a 256^2 SLM: far more traps than
+    resolution cells, so some fields nearly cancel (the smallest |V_m| is about 1/60 of the mean)
+    and the GSW weights w <|V|>/|V_m| multiply those traps' rounding.  The random-superposition
+    mask meets the usual phase bar; after two GSW iterations the map is so ill-conditioned that the
+    FP64 oracle fed the same geometry rounded to FP32 keeps only ~95 % of pixels within 1e-3 rad,
+    so the GPU mask is held to that run.  |V| is held to 1e-4 relative on every trap whose |V_m| is
+    at least a tenth of the mean (on the others a relative bar measures the cancellation, not the
+    arithmetic) and to 1e-5 of the mean |V| absolute on all."""
+    p = W.random_problem(380, 256, 256, 2048, 2)
+    g = run(ctx, algo, p, 2)
+    o = oracle.solve(algo, p.slm, p.xyz, p.theta0, 2)
+    if algo == "rs":
+        assert_phase(to_np(g.phase), o["phi"])
+    else:
+        f32 = lambda a: a.astype(np.float32).astype(np.float64)
+        pert = oracle.solve(algo, p.slm, f32(p.xyz), f32(p.theta0), 2)
+        assert_phase_within_conditioning(to_np(g.phase), o["phi"], pert["phi"])
+    gv, ov = as_complex(to_np(g.V)), o["V"]
+    big = np.abs(ov) >= 0.1 * np.abs(ov).mean()
+    assert_V(gv[big], ov[big])
+    assert np.max(np.abs(gv - ov)) <= 1e-5 * np.abs(ov).mean()
 
 
 def test_contexts_release_device_memory(hot):
@@ -417,8 +482,9 @@ def test_tuning_rejects_unsupported_shapes(hot):
     """Every launch-shape knob accepts only the shapes the library has kernels for; a refused value
     leaves the context usable with its previous settings."""
     with hot.Context(0) as c:
-        for knob, val in (("pixels_per_lane", 3), ("traps_per_lane", 7), ("traps_per_lane", 9),
-                          ("segment", 32), ("sep_waves", 3), ("rows", 3), ("sep_split", 3)):
+        for knob, val in (("pixels_per_lane", 3), ("pixels_per_lane", 4), ("traps_per_lane", 7),
+                          ("traps_per_lane", 9), ("segment", 32), ("sep_waves", 3), ("rows", 3),
+                          ("sep_split", 3), ("fract", 2)):
             with pytest.raises(hot.HotError) as e:
                 c.set_tuning(**{knob: val})
             assert e.value.code == hot.HOT_EINVAL, knob
@@ -648,9 +714,9 @@ def test_separable_1024sq_256_traps(sep):
     g = run(sep, "gsw", p, state=True)
     phi = to_np(g.phase).ravel()
     assert_V(to_np(g.V), oracle.forward(p.slm, p.xyz, phi), what="trap pass at K=40")
-    idx = np.random.default_rng(7).choice(p.slm.n, 4096, replace=False)
+    idx = np.random.default_rng(7).choice(p.slm.n, 65536, replace=False)
     ref = oracle.backward(p.slm, p.xyz, to_np(g.w), to_np(g.theta).astype(np.float64), idx=idx)
-    assert_phase(phi[idx], ref, frac=0.998, what="pixel pass at K=40")
+    assert_phase(phi[idx], ref, what="pixel pass at K=40")
     g3 = run(sep, "gsw", p, 3)
     o3 = oracle_solve("gsw", p, 3)
     assert_phase(to_np(g3.phase), o3["phi"])
