@@ -296,7 +296,7 @@ int prepare(hot_ctx* c, const hot_slm* slm, int B, const int32_t* counts, const 
     // measured slower (GSW 512^2 x 100: 18.8 against 18.0 us per iteration)
     P.rows = P.nt == 256 && c->tune_rows > 0 ? c->tune_rows : 1;
   }
-  P.fgf = row_segments(slm->nx, slm->ny, c->tune_seg > 0 ? c->tune_seg : kSegMax);
+  P.fgf = row_segments(slm->nx, slm->ny, c->tune_seg > 0 ? std::min(c->tune_seg, kSegMax) : kSegMax);
   P.nblk_stored = stored_nblk(P.n);
   {
     // separable: the widest block (most waves sharing one update and one sum per trap) that
@@ -381,6 +381,21 @@ int prepare(hot_ctx* c, const hot_slm* slm, int B, const int32_t* counts, const 
   const double umax = (double)std::max({P.fg.seg_w, P.fgf.seg_w, kBlock * 2});
   const double bound = gmax * umax * umax + std::min(0.25, amax) * umax + 2.5;
   P.fract = c->tune_fract == 1 || bound > 240.0;
+  // the fused kernel's LDS (static part, plus records and K for every (row, span) pair) must fit a
+  // compute unit; for very many traps the planner falls back to one row per block, then to
+  // segments of at most 512 pixels
+  auto iter_lds = [&]() {
+    const int hs = P.nt * P.q / kSpan;
+    return refs_lds_bytes(P.rows * hs, P.mmax) + iter_static_lds(P.nt, P.q, kTplMax, P.rows);
+  };
+  if (iter_lds() > (size_t)kLdsMax && P.rows == 2) P.rows = 1;
+  if (iter_lds() > (size_t)kLdsMax && P.fg.seg_w > 512) {
+    P.fg = row_segments(slm->nx, slm->ny, 512);
+    P.q = P.fg.seg_w > 256 ? 2 : 1;
+    P.nt = 256;
+  }
+  if (iter_lds() > (size_t)kLdsMax)
+    return fail(HOT_EINVAL, "%d traps do not fit the iteration kernel's LDS with this launch shape", P.mmax);
   const int Wi = P.nt / 64, Wf = kBlock / 64;
   P.tpl = c->tune_tpl > 0 ? c->tune_tpl : choose_tpl(counts, B, P.fg.seg_w, Wi, c->tune_amax);
   P.tplf = c->tune_tpl > 0 ? c->tune_tpl : choose_tpl(counts, B, P.fgf.seg_w, Wf, c->tune_amax);
@@ -499,6 +514,7 @@ IterArgs iter_args(hot_ctx* c, const Plan& P, float* phase, int K) {
   a.q = P.q;
   a.tpl = P.tpl;
   a.rows = P.rows;
+  a.mmax = P.mmax;
   if (P.B == 1) a.one = c->h_hd[0];
   a.fract = P.fract;
   a.coef = (const TrapCoef*)c->coef.p;
@@ -566,6 +582,7 @@ int solve(hot_ctx* c, const hot_slm* slm, int B, const int32_t* counts, const do
         a.acc_out = acc_buf(c, P, (k + 1) % 3);
         a.acc_zero = acc_buf(c, P, (k + 2) % 3);
         a.kstat = k - 1;
+        a.phase = k == K ? phase : nullptr;  // only the last mask's phase is returned
         e = launch_iter(s, a);
       }
     } else {
@@ -869,7 +886,7 @@ int hot_forward_V(hot_ctx* c, const hot_slm* slm, int32_t B, const int32_t* M, c
   const int nblk = P.fgf.nblk();
   if ((rc = ensure(c, c->partial, sizeof(float2) * (size_t)P.T * nblk))) return rc;
   const HoloDesc* hdf = (const HoloDesc*)c->hd.p + B;
-  HIP_TRY(launch_forward(c->stream, P.fgf, B, P.tplf, P.fract, (const TrapCoef*)c->coef.p, hdf, phase,
+  HIP_TRY(launch_forward(c->stream, P.fgf, B, P.mmax, P.tplf, P.fract, (const TrapCoef*)c->coef.p, hdf, phase,
                          (float2*)c->partial.p));
   HIP_TRY(launch_reduce(c->stream, B, P.mmax, nblk, (float)(1.0 / (double)P.n), (const float2*)c->partial.p, hdf, V));
   return HOT_OK;
@@ -937,7 +954,7 @@ int hot_time_passes(hot_ctx* c, const hot_slm* slm, int32_t M, const double* xyz
   // stored pixel + trap pass).  A fused kernel reads buffer 0 (filled beforehand by a pass over
   // the theta0 mask), adds into buffer 1 (its sums then wrap around over the repetitions:
   // integers, and unused) and clears buffer 2.
-  IterArgs a = iter_args(c, P, phase, 1);
+  IterArgs a = iter_args(c, P, nullptr, 1);  // as every iteration but a solve's last: no mask stored
   a.upd = 2;
   a.st_in = st[0];
   a.st_out = st[1];
@@ -1002,7 +1019,7 @@ int hot_time_passes(hot_ctx* c, const hot_slm* slm, int32_t M, const double* xyz
     if (separable) return sep_mode(1);
     return stored ? launch_forward_stored(c->stream, P.n, 1, P.mmax, (const float2*)c->amat.p,
                                           (const float2*)c->efield.p, hd, part)
-                  : launch_forward(c->stream, P.fgf, 1, P.tplf, P.fract, coef, hd + 1, phase, part);
+                  : launch_forward(c->stream, P.fgf, 1, P.mmax, P.tplf, P.fract, coef, hd + 1, phase, part);
   };
   hipEvent_t ev[5];
   for (auto& e : ev) HIP_TRY(hipEventCreate(&e));

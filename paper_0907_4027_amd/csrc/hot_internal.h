@@ -53,7 +53,31 @@ struct alignas(16) HoloDesc {
 constexpr int kTplMax = 8;     // traps per lane in the trap pass: 1..6 or 8
 constexpr int kBlock = 256;    // threads of the stand-alone pass kernels
 constexpr int kMaxTraps = 2048;
-constexpr int kSegMax = 1024;  // pixels of a row per trap-pass block
+constexpr int kSegMax = 512;   // pixels of a row per stand-alone trap-pass block
+constexpr int kLdsMax = 160 * 1024;  // LDS of one compute unit (one block may use all of it)
+
+// Spans: a block's row segment is referenced 256 pixels at a time (hot_kernels.hip), so the
+// per-term |u| stays <= kSpan.  The trap pass keeps its pixels in LDS span by span, kSpanStride
+// float4 per span (slices cover < len + 64 entries, plus the read-ahead).
+constexpr int kSpan = 256;
+constexpr int kSpanStride = kSpan + 64 + 4;
+// Pixel-pass records: M records, then zeros up to a multiple of kTrapChunk plus one more chunk.
+constexpr int kTrapChunk = 4;
+__host__ __device__ constexpr int rec_pad(int m) { return (m + 2 * kTrapChunk - 1) / kTrapChunk * kTrapChunk; }
+__host__ __device__ constexpr int k_stride(int mmax) { return (mmax + 3) / 4 * 4; }
+// Dynamic LDS of the direct passes: per (row, span) pair rec_pad(mmax) float4 records and
+// k_stride(mmax) floats K.
+inline size_t refs_lds_bytes(int rows_spans, int mmax) {
+  return (size_t)rows_spans * (16 * (size_t)rec_pad(mmax) + 4 * (size_t)k_stride(mmax));
+}
+// Static LDS of the fused iteration kernel and of the stand-alone trap pass.
+inline size_t iter_static_lds(int nt, int q, int tpl, int rows) {
+  const int hs = nt * q / kSpan, w = nt / 64;
+  return (size_t)rows * hs * kSpanStride * 16 + (size_t)rows * w * 64 * tpl * 8 + 8 * (size_t)nt * rows / 64 * 4;
+}
+inline size_t forward_static_lds(int tpl, int hs) {
+  return (size_t)hs * kSpanStride * 16 + (size_t)(kBlock / 64) * 64 * tpl * 8;
+}
 constexpr int kStoredPpl = 8;  // stored variant: pixels per lane of the trap pass
 inline int stored_nblk(int n) { return (n + 64 * kStoredPpl - 1) / (64 * kStoredPpl); }
 
@@ -76,6 +100,7 @@ struct IterArgs {
   int B = 1;
   int nt = 256, q = 1, tpl = 1;  // threads per row (256/512), pixels per lane (1/2), traps per lane
   int rows = 1;                  // rows per block: 1, or 2 (nt = 256 only)
+  int mmax = 1;                  // most traps of any hologram of the launch (sizes the LDS)
   HoloDesc one{};                // B == 1: the hologram's descriptor (one.m > 0), passed by value
   bool fract = false;
   const TrapCoef* coef = nullptr;
@@ -91,7 +116,7 @@ struct IterArgs {
   int kstat = 0, stat_stride = 1;
   int upd = 0;                   // 0 none, 1 GS, 2 GSW
   int* flag = nullptr;
-  float* phase = nullptr;
+  float* phase = nullptr;  // the mask is written when not null
 };
 
 // ---- launchers (hot_kernels.hip); all enqueue on `s` and return hipError_t ----
@@ -114,8 +139,8 @@ hipError_t launch_backward(hipStream_t s, int nx, int ny, int B, bool fract, int
 
 // Trap pass alone: per-block partial sums of e^{i 2pi (phi - Delta)} -> partial[(off + m) * nblk + blk].
 // `tpl` is the traps-per-lane count every hologram of the launch was laid out for.
-hipError_t launch_forward(hipStream_t s, const FwdGeom& fg, int B, int tpl, bool fract, const TrapCoef* coef,
-                          const HoloDesc* hd, const float* phase, float2* partial);
+hipError_t launch_forward(hipStream_t s, const FwdGeom& fg, int B, int mmax, int tpl, bool fract,
+                          const TrapCoef* coef, const HoloDesc* hd, const float* phase, float2* partial);
 
 // Fixed-order sum of the partials: V (interleaved re/im) = sum / N.
 hipError_t launch_reduce(hipStream_t s, int B, int mmax, int nblk, float inv_n, const float2* partial,

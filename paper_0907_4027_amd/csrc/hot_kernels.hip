@@ -256,8 +256,7 @@ __device__ void update_traps(VGet vmem, const TrapState* __restrict__ st_in, int
 // the records it needs (a scalar load in the loop would force a wait for all of them).
 // `rec` holds M records followed by zero records up to round_up(M, kTrapChunk) + kTrapChunk
 // (w = 0: they add nothing).
-constexpr int kTrapChunk = 4;
-__host__ __device__ constexpr int rec_pad(int m) { return (m + 2 * kTrapChunk - 1) / kTrapChunk * kTrapChunk; }
+// (kTrapChunk and rec_pad are in hot_internal.h.)
 
 template <int Q, bool FRACT>
 __device__ __forceinline__ void pixel_chunk(const float4* c, const float* U, const float* U2, float* sr, float* si) {
@@ -334,73 +333,62 @@ __device__ __forceinline__ void pad_records(float4* rec, int M) {
   for (int m = M + (int)threadIdx.x; m < rec_pad(M); m += NT) rec[m] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
 }
 
-// Trap pass over one row segment whose pixels (phi_rev, u, u^2, mask) sit in LDS `px`
-// (len real entries, zero-padded to S * slen), u relative to the block's reference.  Each wave
-// is split into A slices of G lanes; lane (slice s, position l) owns traps l, l+G, ...,
-// l+(TPL-1)G of a chunk and loops over the pixels of its slice:
+// Spans.  The pixels of a row segment are referenced span by span: span h holds the pixels
+// [kSpan h, kSpan (h + 1)) of the segment, with its own centre Uc_h, slope a'_h and constant K_h
+// (hot_internal.h), so |u| <= kSpan in the per-term argument whatever the segment's width.  The
+// trap pass's pixels sit in LDS span by span, kSpanStride entries per span (zero-padded).
+// (kSpan, kSpanStride and the LDS sizes are in hot_internal.h.)
+
+// Trap pass over one row segment (per half of a block with ROWS = 2) whose pixels
+// (phi_rev, u, u^2, mask) sit span by span in LDS `pxh` (len real entries).  The W waves of a half
+// share the HS spans, WS = W / HS waves per span; each wave is split into A slices of G lanes;
+// lane (slice s, position l) owns traps l, l+G, ..., l+(TPL-1)G of a chunk and loops over the
+// pixels of its slice:
 //   t = phi - a'_m u - g_m u^2               2 VALU
 //   sin t, cos t                             2 transcendental
 //   acc += mask (cos t, sin t)              2 VALU
-// The S slice partials of each trap are then summed in slice order through LDS `red`.  The
-// block constant K_m of Eq. 2 is left out of the pixel sums: the sum of each trap over a row is
-// turned by e^{-i 2pi K_m} once, by the thread that sums its slices, and handed to store(m, sum).
-// The lane coefficients of a chunk are -a' and -g of the traps the lane owns (the trap's K for
-// row h sits at kt[h * kt_stride + m]).  Slots past M take trap M - 1's coefficients (always a
-// valid read, and the arguments stay in the sin/cos domain); their sums are never written out.
+// with a'_m and g_m the coefficients of its span's records.  The slice partials of each trap are
+// then summed in slice order through LDS `red`, span by span; the span constant K_m of Eq. 2 is
+// left out of the pixel sums: each span's sum is turned by e^{-i 2pi K_m} once, by the thread that
+// sums its slices, and store(m, sum) gets the block's sum over its spans and rows.  Slots past M
+// take trap M - 1's coefficients (always a valid read, and the arguments stay in the sin/cos
+// domain); their sums are never written out.
 template <int TPL>
 struct LaneCoef {
   float na[TPL], ng[TPL];
 };
-// ... from the FP64 coefficients in global memory (a' formed here, as the records form it) ...
 template <int TPL>
-__device__ __forceinline__ LaneCoef<TPL> load_lane_coef(const TrapCoef* __restrict__ cf, int M, int G, int k0,
-                                                        double Uc) {
+__device__ __forceinline__ LaneCoef<TPL> lane_coef(const float4* rec, int M, int G, int k0) {
   const int lane = threadIdx.x & 63;
   const int tl = lane - lane / G * G;
   LaneCoef<TPL> lc;
 #pragma unroll
   for (int k = 0; k < TPL; ++k) {
-    const TrapCoef c = cf[min(k0 + tl + k * G, M - 1)];
-    lc.na[k] = -block_slope(c, Uc);
-    lc.ng[k] = -c.gf;
-  }
-  return lc;
-}
-// ... or, for the first chunk, from the staged pixel-pass records {a', g, ., .} in LDS.
-template <int TPL>
-__device__ __forceinline__ LaneCoef<TPL> lane_coef_from_records(const float4* rec, int M, int G) {
-  const int lane = threadIdx.x & 63;
-  const int tl = lane - lane / G * G;
-  LaneCoef<TPL> lc;
-#pragma unroll
-  for (int k = 0; k < TPL; ++k) {
-    const float4 r = rec[min(tl + k * G, M - 1)];
+    const float4 r = rec[min(k0 + tl + k * G, M - 1)];
     lc.na[k] = -r.x;
     lc.ng[k] = -r.y;
   }
   return lc;
 }
 
-// `first` holds the lane's coefficients of the first chunk (k0 = 0), read by the caller before
-// its own global stores, so that waiting for them does not wait for those stores too.
-// With ROWS = 2 the block is two halves of W waves, each passing over its own row (px and len of
-// the calling thread's half).  store(m, sum) gets the block's sum over its rows.
-template <int W, int TPL, bool FRACT, int ROWS, class Store>
-__device__ __forceinline__ void trap_pass_block(const TrapCoef* __restrict__ cf, double Uc, const float* kt,
-                                                int kt_stride, int M, int G, int A, const float4* px, int len,
-                                                float2* red, Store store, const LaneCoef<TPL>& first) {
-  constexpr int NB = ROWS * W * 64;
+template <int W, int HS, int TPL, bool FRACT, int ROWS, class Store>
+__device__ __forceinline__ void trap_pass_block(const float4* rec, int rp, const float* kt, int mp, int M, int G,
+                                                int A, const float4* pxh, int len, float2* red, Store store) {
+  static_assert(W % HS == 0, "whole waves per span");
+  constexpr int NB = ROWS * W * 64, WS = W / HS;
   const int half = (int)threadIdx.x / (W * 64);
   const int wave = ((int)threadIdx.x >> 6) - half * W, lane = threadIdx.x & 63;
   const int s = lane / G, tl = lane - s * G;
   const bool active = s < A;
-  const int S = W * A;
-  const int slen = (len + S - 1) / S;
-  const int sidx = wave * A + min(s, A - 1);
-  const float4* mine = px + sidx * slen;
+  const int h = wave / WS, lw = wave - h * WS;  // the wave's span, and its place among the span's waves
+  const int lh = min(max(len - kSpan * h, 0), kSpan);
+  const int SA = WS * A;  // slices per span
+  const int slen = (lh + SA - 1) / SA;
+  const float4* mine = pxh + h * kSpanStride + (lw * A + min(s, A - 1)) * slen;
+  const float4* rech = rec + (half * HS + h) * rp;
   const int nslot = G * TPL;
   for (int k0 = 0; k0 < M; k0 += nslot) {
-    const LaneCoef<TPL> lc = k0 == 0 ? first : load_lane_coef<TPL>(cf, M, G, k0, Uc);
+    const LaneCoef<TPL> lc = lane_coef<TPL>(rech, M, G, k0);
     float na[TPL], ng[TPL], accr[TPL], acci[TPL];
 #pragma unroll
     for (int k = 0; k < TPL; ++k) {
@@ -412,7 +400,7 @@ __device__ __forceinline__ void trap_pass_block(const TrapCoef* __restrict__ cf,
     // Two pixels per half step, from two register pairs that alternate: one pair is summed while
     // the next is read (offsets hidden from the optimiser as in the pixel pass).  Full double
     // steps run while 4 pixels remain, then the last 1-3 pixels one pair and one single at a
-    // time.  Reads reach at most mine[slen + 1], inside px (S * slen + 3 entries).
+    // time.  Reads reach at most mine[slen + 1], inside the span's region (SA slen + 2 entries).
     auto term1 = [&](const float4& p0) {
 #pragma unroll
       for (int k = 0; k < TPL; ++k) {
@@ -456,10 +444,11 @@ __device__ __forceinline__ void trap_pass_block(const TrapCoef* __restrict__ cf,
     } else if (rest == 1) {
       term1(pa);
     }
-    __syncthreads();  // red[] is free: earlier readers (previous chunk, or the pixel pass) are done
+    __syncthreads();  // red[] is free: its readers of the previous chunk are done
     if (active) {
 #pragma unroll
-      for (int k = 0; k < TPL; ++k) red[(half * S + sidx) * nslot + tl + k * G] = make_float2(accr[k], acci[k]);
+      for (int k = 0; k < TPL; ++k)
+        red[(half * W * A + wave * A + s) * nslot + tl + k * G] = make_float2(accr[k], acci[k]);
     }
     __syncthreads();
     for (int i = threadIdx.x; i < nslot; i += NB) {
@@ -467,26 +456,26 @@ __device__ __forceinline__ void trap_pass_block(const TrapCoef* __restrict__ cf,
       if (m < M) {
         float2 acc = make_float2(0.0f, 0.0f);
 #pragma unroll
-        for (int h = 0; h < ROWS; ++h) {
-          const float kh = kt[h * kt_stride + m];
-          // the slices in order; the reads go out in groups so that their latencies overlap
-          const float2* rp = red + h * S * nslot + i;
+        for (int hr = 0; hr < ROWS * HS; ++hr) {  // (row half, span) pairs
+          const float kh = kt[hr * mp + m];
+          // the span's slices in order; the reads go out in groups so that their latencies overlap
+          const float2* rp2 = red + hr * SA * nslot + i;
           float sr = 0.0f, si = 0.0f;
           int s2 = 0;
-          for (; s2 + 8 <= S; s2 += 8) {
+          for (; s2 + 8 <= SA; s2 += 8) {
             float2 v[8];
 #pragma unroll
-            for (int u = 0; u < 8; ++u) v[u] = rp[(s2 + u) * nslot];
+            for (int u = 0; u < 8; ++u) v[u] = rp2[(s2 + u) * nslot];
 #pragma unroll
             for (int u = 0; u < 8; ++u) {
               sr += v[u].x;
               si += v[u].y;
             }
           }
-          if (s2 + 4 <= S) {
+          if (s2 + 4 <= SA) {
             float2 v[4];
 #pragma unroll
-            for (int u = 0; u < 4; ++u) v[u] = rp[(s2 + u) * nslot];
+            for (int u = 0; u < 4; ++u) v[u] = rp2[(s2 + u) * nslot];
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
               sr += v[u].x;
@@ -494,9 +483,9 @@ __device__ __forceinline__ void trap_pass_block(const TrapCoef* __restrict__ cf,
             }
             s2 += 4;
           }
-          for (; s2 < S; ++s2) {
-            sr += rp[s2 * nslot].x;
-            si += rp[s2 * nslot].y;
+          for (; s2 < SA; ++s2) {
+            sr += rp2[s2 * nslot].x;
+            si += rp2[s2 * nslot].y;
           }
           const float cs = __builtin_amdgcn_cosf(kh), sn = __builtin_amdgcn_sinf(kh);
           acc.x += __builtin_fmaf(sr, cs, si * sn);  // (sr + i si) e^{-i 2pi K}
@@ -508,24 +497,46 @@ __device__ __forceinline__ void trap_pass_block(const TrapCoef* __restrict__ cf,
   }
 }
 
+// Stage the records and K of trap m for the block's spans of a row segment starting at column
+// cbeg with lseg pixels, for its ROWS rows (row coordinate of row hr: Vb + 2 hr).
+template <int HS, int ROWS>
+__device__ __forceinline__ void stage_spans(float4* rec, int rp, float* kt, int mp, int m, const TrapCoef& c, int nx,
+                                            int cbeg, int lseg, int Vb, float theta_rev, float w) {
+#pragma unroll
+  for (int h = 0; h < HS; ++h) {
+    const int cc = centre_col(cbeg + kSpan * h, min(max(lseg - kSpan * h, 1), kSpan));
+    const double Uc = (double)(2 * cc - (nx - 1));
+    const float ap = block_slope(c, Uc);
+#pragma unroll
+    for (int hr = 0; hr < ROWS; ++hr) {
+      const float k = block_const(c, Uc, (double)(Vb + 2 * hr));
+      stage_record(rec + (hr * HS + h) * rp, m, ap, c.gf, k, theta_rev, w);
+      kt[(hr * HS + h) * mp + m] = k;
+    }
+  }
+}
+
 // ------------------------------------------------------------------ fused iteration kernel
 //
 // Grid (nseg, ceil(ny / ROWS), B), ROWS * NT threads.  Each half of NT threads passes over one row
-// segment (seg_w <= NT * Q pixels) of row ROWS * blockIdx.y + half; both halves share the update
-// and add one sum per trap (ROWS = 2 halves the update work and the atomic adds per row).
+// segment (seg_w <= NT * Q pixels, HS = NT Q / kSpan spans) of row ROWS * blockIdx.y + half; both
+// halves share the update and add one sum per trap (ROWS = 2 halves the update work and the
+// atomic adds per row).
 //   upd = 0: use st_in as is;  1/2: GS/GSW update from V of the previous mask and st_in,
 //   recomputed by every block; block (0, 0, b) also writes the new state to st_out and the
 //   figures of merit of that V to stats[b][kstat].
 //   V is not a separate array: the previous launch added each block's trap sums to acc_in as
 //   fixed-point words (pack_sum: re and im in one 64-bit atomic add), one region per XCD (the
 //   XCC_ID of the adding wave) so that the atomics of different XCDs do not contend; integer
-//   sums do not depend on the order of the adds, so the result is deterministic.  This launch adds its own sums to
-//   acc_out, and block (0, 0, b) clears hologram b's part of acc_zero for the launch after next.
-//   acc_in is read even when upd == 0 (it must be a valid buffer; the values are then unused).
+//   sums do not depend on the order of the adds, so the result is deterministic.  This launch
+//   adds its own sums to acc_out, and block (0, 0, b) clears hologram b's part of acc_zero for the
+//   launch after next.  acc_in is read even when upd == 0 (it must be a valid buffer; the values
+//   are then unused).
 //   one.m > 0: a single hologram whose descriptor comes by value, so no load waits for it.
 //   The arguments the first loads need lead the list (they fit the SGPRs that the kernel
 //   arguments are preloaded into at wave launch).
-// Writes phase (radians).
+//   Writes the phase (radians) when `phase` is not null (the host passes it for the last mask only).
+//   Dynamic LDS: refs_lds_bytes(ROWS * HS, mmax) for records and K (mmax >= every hologram's M).
 template <int NT, int Q, int TPL, bool FRACT, int ROWS>
 __global__ void __launch_bounds__(NT * ROWS)
 k_iter(HoloDesc one, const TrapCoef* __restrict__ coef, const TrapState* __restrict__ st_in,
@@ -533,31 +544,28 @@ k_iter(HoloDesc one, const TrapCoef* __restrict__ coef, const TrapState* __restr
        TrapState* __restrict__ st_out, unsigned long long* __restrict__ acc_out,
        unsigned long long* __restrict__ acc_zero, int T, float scale, float unscale,
        float* __restrict__ stats, int kstat, int stat_stride, int upd, int* __restrict__ flag, int nx, int ny,
-       int seg_w, float* __restrict__ phase) {
-  constexpr int W = NT / 64;        // waves per half
-  constexpr int NB = NT * ROWS;     // threads of the block
-  constexpr int PXN = NT * Q + 136;  // slices cover < len + S <= len + 128 entries, plus 3 read ahead
-  constexpr int REDN = ROWS * W * 64 * TPL;            // float2 slice partials of both halves
-  constexpr int RECN = rec_pad(kMaxTraps);             // float4 pixel-pass records of one row
-  constexpr int UN = 2 * ROWS * RECN > REDN ? 2 * ROWS * RECN : REDN;  // in float2 units
-  __shared__ float4 pxs[ROWS * PXN];
-  __shared__ float2 ubuf[UN];  // pixel-pass records (one set per row), then slice partials
-  __shared__ float kts[ROWS * kMaxTraps];  // K of each trap and row (the trap pass's turn)
+       int seg_w, int mmax, float* __restrict__ phase) {
+  constexpr int W = NT / 64;           // waves per half
+  constexpr int NB = NT * ROWS;        // threads of the block
+  constexpr int HS = NT * Q / kSpan;   // spans per segment
+  static_assert(HS >= 1 && NT * Q == HS * kSpan, "segments of whole spans");
+  __shared__ float4 pxs[ROWS * HS * kSpanStride];
+  __shared__ float2 red[ROWS * W * 64 * TPL];  // slice partials of both halves
   __shared__ float sh[8 * NB / 64];
+  extern __shared__ float4 refs[];
+  const int rp = rec_pad(mmax), mp = k_stride(mmax);
+  float* kts = reinterpret_cast<float*>(refs + ROWS * HS * rp);
   const int b = blockIdx.z, sg = blockIdx.x;
   const int half = ROWS == 1 ? 0 : (int)threadIdx.x / NT, tid = (int)threadIdx.x - half * NT;
   const int r = blockIdx.y * ROWS + half;
   const HoloDesc d = one.m > 0 ? one : hd[b];
   const int M = d.m, off = d.off, G = d.g, A = d.a;
   const TrapCoef* __restrict__ cf = coef + off;
-  float4* rec_all = reinterpret_cast<float4*>(ubuf);
-  float4* px = pxs + half * PXN;
+  float4* px = pxs + half * HS * kSpanStride;
   const bool lead = sg == 0 && blockIdx.y == 0;
   const VAcc vacc{acc_in, T, off, unscale};
-  // the block's reference column (the centre of its segment; the same for both rows)
-  const int cbeg = sg * seg_w;
-  const int cc = centre_col(cbeg, min(nx, cbeg + seg_w) - cbeg);
-  const double Uc = (double)(2 * cc - (nx - 1));
+  const int cbeg = sg * seg_w, lseg = min(nx, cbeg + seg_w) - cbeg;
+  const int Vb = 2 * (int)(blockIdx.y * ROWS) - (ny - 1);
 
   // Every read of the block's own trap data is issued here, unconditionally (threads past M read
   // trap M - 1 and ignore it), so the update waits for one memory round trip.
@@ -572,15 +580,8 @@ k_iter(HoloDesc one, const TrapCoef* __restrict__ coef, const TrapState* __restr
     }
   }
   auto coef_of = [&](int m) { return m == (int)threadIdx.x ? c_first : cf[m]; };
-  // records and K of trap m for every row of the block
   auto stage = [&](int m, const TrapCoef& c, const TrapState& s) {
-    const float ap = block_slope(c, Uc);
-#pragma unroll
-    for (int h = 0; h < ROWS; ++h) {
-      const float k = block_const(c, Uc, (double)(2 * (int)(blockIdx.y * ROWS + h) - (ny - 1)));
-      stage_record(rec_all + h * RECN, m, ap, c.gf, k, s.theta_rev, s.w);
-      kts[h * kMaxTraps + m] = k;
-    }
+    stage_spans<HS, ROWS>(refs, rp, kts, mp, m, c, nx, cbeg, lseg, Vb, s.theta_rev, s.w);
   };
   if (upd == 0) {
     for (int m = threadIdx.x; m < M; m += NB) stage(m, coef_of(m), m == (int)threadIdx.x ? s_first : st_in[off + m]);
@@ -593,53 +594,61 @@ k_iter(HoloDesc one, const TrapCoef* __restrict__ coef, const TrapState* __restr
                                                  lead ? stats + 3 * ((size_t)b * stat_stride + kstat) : nullptr,
                                                  lead ? flag : nullptr, emit, v_first, s_first);
   }
-#pragma unroll
-  for (int h = 0; h < ROWS; ++h) pad_records<NB>(rec_all + h * RECN, M);
+  for (int hs = 0; hs < ROWS * HS; ++hs) pad_records<NB>(refs + hs * rp, M);
   __syncthreads();
 
-  const int len = r < ny ? min(nx, cbeg + seg_w) - cbeg : 0;  // a missing last row has no pixels
+  // pixel pass: pixel q of the lane is pixel i = Q tid + q of the segment (adjacent pixels, so the
+  // Q pixels of a lane and the 64 Q pixels of a wave lie in one span), at u = 2 (column - the
+  // span's centre); one record stream per wave
+  const int len = r < ny ? lseg : 0;  // a missing last row has no pixels
+  const int h0 = Q * tid / kSpan;
+  const int cc0 = centre_col(cbeg + kSpan * h0, min(max(lseg - kSpan * h0, 1), kSpan));
   float u[Q], u2[Q], sr[Q], si[Q];
 #pragma unroll
   for (int q = 0; q < Q; ++q) {
-    u[q] = (float)(2 * (cbeg + tid + q * NT - cc));
+    u[q] = (float)(2 * (cbeg + Q * tid + q - cc0));
     u2[q] = u[q] * u[q];
     sr[q] = 0.0f;
     si[q] = 0.0f;
   }
-  pixel_terms<Q, FRACT>(rec_all + half * RECN, M, u, u2, sr, si);
-  // the trap pass's first-chunk coefficients, from the records while they are still in LDS
-  const LaneCoef<TPL> lane_first = lane_coef_from_records<TPL>(rec_all, M, G);
-  float* __restrict__ prow = phase + (size_t)b * nx * ny + (size_t)r * nx + cbeg;
+  pixel_terms<Q, FRACT>(refs + (half * HS + h0) * rp, M, u, u2, sr, si);
+  float* __restrict__ prow = phase ? phase + (size_t)b * nx * ny + (size_t)r * nx + cbeg : nullptr;
 #pragma unroll
   for (int q = 0; q < Q; ++q) {
-    const int i = tid + q * NT;
+    const int i = Q * tid + q;
+    float4* slot = px + h0 * kSpanStride + (i - kSpan * h0);
     if (i < len) {
       const float ph = phase_of(si[q], sr[q]);
-      prow[i] = ph;
-      px[i] = make_float4(ph * kInv2Pi, u[q], u2[q], 1.0f);
+      if (prow) prow[i] = ph;
+      *slot = make_float4(ph * kInv2Pi, u[q], u2[q], 1.0f);
     } else {
-      px[i] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+      *slot = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
     }
   }
-  for (int i = NT * Q + tid; i < PXN; i += NT) px[i] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+  for (int i = tid; i < HS * (kSpanStride - kSpan); i += NT) {  // each span's padding
+    const int h = i / (kSpanStride - kSpan);
+    px[h * kSpanStride + kSpan + (i - h * (kSpanStride - kSpan))] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+  }
   __syncthreads();
   unsigned long long* __restrict__ mine = acc_out + (size_t)(xcc_id() & (kAccRegions - 1)) * T + off;
   auto add_sum = [&](int m, float2 v) {
     __hip_atomic_fetch_add(mine + m, pack_sum(v, scale), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   };
-  trap_pass_block<W, TPL, FRACT, ROWS>(cf, Uc, kts, kMaxTraps, M, G, A, px, len, ubuf, add_sum, lane_first);
+  trap_pass_block<W, HS, TPL, FRACT, ROWS>(refs, rp, kts, mp, M, G, A, px, len, red, add_sum);
 }
 
 // ------------------------------------------------------------------ stand-alone passes
 //
 // Pixel pass alone.  MODE 0 writes phase = arg S in [0, 2pi].  MODE 1 is the adjoint of
 // Eq. 1: with w e^{i theta} := G_m = dL/dRe V_m + i dL/dIm V_m it writes
-// grad[j] = (1/N) Im(e^{-i phi_j} S_j) for the given phase.
+// grad[j] = (1/N) Im(e^{-i phi_j} S_j) for the given phase.  A block covers kBlock Q <= kSpan
+// pixels of a row: one span.
 template <int Q, bool FRACT, int MODE>
 __global__ void __launch_bounds__(kBlock)
 k_backward(const TrapCoef* __restrict__ coef, const TrapState* __restrict__ st, const HoloDesc* __restrict__ hd,
            int nx, int ny, float* __restrict__ phase, const float* __restrict__ G, float* __restrict__ grad,
            float inv_n) {
+  static_assert(kBlock * Q <= kSpan, "one span per block");
   __shared__ float4 rec[rec_pad(kMaxTraps)];
   const int b = blockIdx.z, r = blockIdx.y;
   const int M = hd[b].m, off = hd[b].off;
@@ -690,32 +699,33 @@ k_backward(const TrapCoef* __restrict__ coef, const TrapState* __restrict__ st, 
   }
 }
 
-// Trap pass alone on a given phase mask: block = one row segment, kBlock threads.
-template <int TPL, bool FRACT>
+// Trap pass alone on a given phase mask: block = one row segment of HS spans, kBlock threads.
+// Dynamic LDS: refs_lds_bytes(HS, mmax).
+template <int TPL, bool FRACT, int HS>
 __global__ void __launch_bounds__(kBlock)
 k_forward(const TrapCoef* __restrict__ coef, const HoloDesc* __restrict__ hd, const float* __restrict__ phase,
-          int nx, int ny, int seg_w, int nseg, float2* __restrict__ partial) {
+          int nx, int ny, int seg_w, int nseg, int mmax, float2* __restrict__ partial) {
   constexpr int W = kBlock / 64;
-  __shared__ float4 px[kSegMax + 72];  // slices cover < len + S <= len + 64 entries, plus 3 read ahead
+  __shared__ float4 px[HS * kSpanStride];
   __shared__ float2 red[W * 64 * TPL];
-  __shared__ float kt[kMaxTraps];
+  extern __shared__ float4 refs[];
+  const int rp = rec_pad(mmax), mp = k_stride(mmax);
+  float* kts = reinterpret_cast<float*>(refs + HS * rp);
   const int b = blockIdx.z, r = blockIdx.y, sg = blockIdx.x;
   const int M = hd[b].m, G = hd[b].g, A = hd[b].a, off = hd[b].off;
   const TrapCoef* __restrict__ cf = coef + off;
   const int cbeg = sg * seg_w;
   const int len = min(nx, cbeg + seg_w) - cbeg;
-  const int cc = centre_col(cbeg, len);
-  const double Uc = (double)(2 * cc - (nx - 1)), Vr = (double)(2 * r - (ny - 1));
-  const int S = W * A;
-  const int padded = S * ((len + S - 1) / S) + 4;  // zeros past the last slice for the read-ahead
+  for (int m = threadIdx.x; m < M; m += kBlock)
+    stage_spans<HS, 1>(refs, rp, kts, mp, m, cf[m], nx, cbeg, len, 2 * r - (ny - 1), 0.0f, 0.0f);
   const float* __restrict__ ph = phase + (size_t)b * nx * ny + (size_t)r * nx + cbeg;
-  const LaneCoef<TPL> lane_first = load_lane_coef<TPL>(cf, M, G, 0, Uc);
-  for (int m = threadIdx.x; m < M; m += kBlock) kt[m] = block_const(cf[m], Uc, Vr);
-  for (int i = threadIdx.x; i < padded; i += kBlock) {
-    if (i < len) {
-      const float u = (float)(2 * (cbeg + i - cc));
+  for (int i = threadIdx.x; i < HS * kSpanStride; i += kBlock) {
+    const int h = i / kSpanStride, l = i - h * kSpanStride, c = kSpan * h + l;  // pixel c of the segment
+    if (l < kSpan && c < len) {
+      const int cc = centre_col(cbeg + kSpan * h, min(len - kSpan * h, kSpan));
+      const float u = (float)(2 * (cbeg + c - cc));
       // any phase the caller passes, wrapped to one period (exact)
-      px[i] = make_float4(__builtin_amdgcn_fractf(ph[i] * kInv2Pi), u, u * u, 1.0f);
+      px[i] = make_float4(__builtin_amdgcn_fractf(ph[c] * kInv2Pi), u, u * u, 1.0f);
     } else {
       px[i] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
     }
@@ -723,8 +733,8 @@ k_forward(const TrapCoef* __restrict__ coef, const HoloDesc* __restrict__ hd, co
   __syncthreads();
   const int nblk = ny * nseg;
   float2* __restrict__ out = partial + (size_t)off * nblk + r * nseg + sg;
-  trap_pass_block<W, TPL, FRACT, 1>(cf, Uc, kt, 0, M, G, A, px, len, red,
-                                    [&](int m, float2 v) { out[(size_t)m * nblk] = v; }, lane_first);
+  trap_pass_block<W, HS, TPL, FRACT, 1>(refs, rp, kts, mp, M, G, A, px, len, red,
+                                        [&](int m, float2 v) { out[(size_t)m * nblk] = v; });
 }
 
 // ------------------------------------------------------------------ reduce, update, finalize
@@ -1342,11 +1352,18 @@ __global__ void k_import_w(const float* __restrict__ w0, TrapState* __restrict__
 
 template <int NT, int Q, int TPL, bool FRACT, int ROWS>
 hipError_t iter_rows(hipStream_t s, const IterArgs& a) {
-  if (a.fg.seg_w > NT * Q || !a.acc_in || !a.acc_out || !a.acc_zero || a.T < 1) return hipErrorInvalidValue;
+  constexpr int HS = NT * Q / kSpan;
+  if (a.fg.seg_w > NT * Q || !a.acc_in || !a.acc_out || !a.acc_zero || a.T < 1 || a.mmax < 1) return hipErrorInvalidValue;
+  const size_t dyn = refs_lds_bytes(ROWS * HS, a.mmax);
+  if (dyn + iter_static_lds(NT, Q, TPL, ROWS) > (size_t)kLdsMax) return hipErrorInvalidValue;
+  static const hipError_t attr = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_iter<NT, Q, TPL, FRACT, ROWS>),
+                                                     hipFuncAttributeMaxDynamicSharedMemorySize,
+                                                     kLdsMax - (int)iter_static_lds(NT, Q, TPL, ROWS));
+  if (attr != hipSuccess) return attr;
   dim3 grid(a.fg.nseg, (a.fg.ny + ROWS - 1) / ROWS, a.B);
-  hipLaunchKernelGGL((k_iter<NT, Q, TPL, FRACT, ROWS>), grid, dim3(NT * ROWS), 0, s, a.B == 1 ? a.one : HoloDesc{}, a.coef,
-                     a.st_in, a.acc_in, a.hd, a.st_out, a.acc_out, a.acc_zero, a.T, a.acc_scale, a.acc_unscale, a.stats, a.kstat, a.stat_stride,
-                     a.upd, a.flag, a.fg.nx, a.fg.ny, a.fg.seg_w, a.phase);
+  hipLaunchKernelGGL((k_iter<NT, Q, TPL, FRACT, ROWS>), grid, dim3(NT * ROWS), dyn, s, a.B == 1 ? a.one : HoloDesc{},
+                     a.coef, a.st_in, a.acc_in, a.hd, a.st_out, a.acc_out, a.acc_zero, a.T, a.acc_scale, a.acc_unscale,
+                     a.stats, a.kstat, a.stat_stride, a.upd, a.flag, a.fg.nx, a.fg.ny, a.fg.seg_w, a.mmax, a.phase);
   return hipGetLastError();
 }
 
@@ -1394,24 +1411,35 @@ hipError_t backward_q(hipStream_t s, int nx, int ny, int B, const TrapCoef* coef
 template <bool FRACT, int MODE>
 hipError_t backward_sel(hipStream_t s, int q, int nx, int ny, int B, const TrapCoef* coef, const TrapState* st,
                         const HoloDesc* hd, float* phase, const float* G, float* grad, float inv_n) {
-  switch (q) {
-    case 1: return backward_q<1, FRACT, MODE>(s, nx, ny, B, coef, st, hd, phase, G, grad, inv_n);
-    case 2: return backward_q<2, FRACT, MODE>(s, nx, ny, B, coef, st, hd, phase, G, grad, inv_n);
-    default: return hipErrorInvalidValue;
-  }
+  // one pixel per lane: a block is one span (kBlock = kSpan pixels)
+  if (q != 1) return hipErrorInvalidValue;
+  return backward_q<1, FRACT, MODE>(s, nx, ny, B, coef, st, hd, phase, G, grad, inv_n);
+}
+
+template <int TPL, bool FRACT, int HS>
+hipError_t forward_hs(hipStream_t s, const FwdGeom& fg, int B, int mmax, const TrapCoef* coef, const HoloDesc* hd,
+                      const float* phase, float2* partial) {
+  const size_t dyn = refs_lds_bytes(HS, mmax);
+  if (dyn + forward_static_lds(TPL, HS) > (size_t)kLdsMax) return hipErrorInvalidValue;
+  static const hipError_t attr = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_forward<TPL, FRACT, HS>),
+                                                     hipFuncAttributeMaxDynamicSharedMemorySize,
+                                                     kLdsMax - (int)forward_static_lds(TPL, HS));
+  if (attr != hipSuccess) return attr;
+  dim3 grid(fg.nseg, fg.ny, B);
+  hipLaunchKernelGGL((k_forward<TPL, FRACT, HS>), grid, dim3(kBlock), dyn, s, coef, hd, phase, fg.nx, fg.ny, fg.seg_w,
+                     fg.nseg, mmax, partial);
+  return hipGetLastError();
 }
 
 template <int TPL>
-hipError_t forward_t(hipStream_t s, const FwdGeom& fg, int B, bool fract, const TrapCoef* coef, const HoloDesc* hd,
-                     const float* phase, float2* partial) {
-  dim3 grid(fg.nseg, fg.ny, B);
+hipError_t forward_t(hipStream_t s, const FwdGeom& fg, int B, int mmax, bool fract, const TrapCoef* coef,
+                     const HoloDesc* hd, const float* phase, float2* partial) {
+  const bool two = fg.seg_w > kSpan;
   if (fract)
-    hipLaunchKernelGGL((k_forward<TPL, true>), grid, dim3(kBlock), 0, s, coef, hd, phase, fg.nx, fg.ny, fg.seg_w,
-                       fg.nseg, partial);
-  else
-    hipLaunchKernelGGL((k_forward<TPL, false>), grid, dim3(kBlock), 0, s, coef, hd, phase, fg.nx, fg.ny, fg.seg_w,
-                       fg.nseg, partial);
-  return hipGetLastError();
+    return two ? forward_hs<TPL, true, 2>(s, fg, B, mmax, coef, hd, phase, partial)
+               : forward_hs<TPL, true, 1>(s, fg, B, mmax, coef, hd, phase, partial);
+  return two ? forward_hs<TPL, false, 2>(s, fg, B, mmax, coef, hd, phase, partial)
+             : forward_hs<TPL, false, 1>(s, fg, B, mmax, coef, hd, phase, partial);
 }
 
 }  // namespace
@@ -1431,17 +1459,17 @@ hipError_t launch_backward(hipStream_t s, int nx, int ny, int B, bool fract, int
                : backward_sel<false, 1>(s, q, nx, ny, B, coef, st, hd, phase, G, grad, inv_n);
 }
 
-hipError_t launch_forward(hipStream_t s, const FwdGeom& fg, int B, int tpl, bool fract, const TrapCoef* coef,
-                          const HoloDesc* hd, const float* phase, float2* partial) {
-  if (fg.seg_w > kSegMax) return hipErrorInvalidValue;
+hipError_t launch_forward(hipStream_t s, const FwdGeom& fg, int B, int mmax, int tpl, bool fract,
+                          const TrapCoef* coef, const HoloDesc* hd, const float* phase, float2* partial) {
+  if (fg.seg_w > kSegMax || mmax < 1) return hipErrorInvalidValue;
   switch (tpl) {
-    case 1: return forward_t<1>(s, fg, B, fract, coef, hd, phase, partial);
-    case 2: return forward_t<2>(s, fg, B, fract, coef, hd, phase, partial);
-    case 3: return forward_t<3>(s, fg, B, fract, coef, hd, phase, partial);
-    case 4: return forward_t<4>(s, fg, B, fract, coef, hd, phase, partial);
-    case 5: return forward_t<5>(s, fg, B, fract, coef, hd, phase, partial);
-    case 6: return forward_t<6>(s, fg, B, fract, coef, hd, phase, partial);
-    case 8: return forward_t<8>(s, fg, B, fract, coef, hd, phase, partial);
+    case 1: return forward_t<1>(s, fg, B, mmax, fract, coef, hd, phase, partial);
+    case 2: return forward_t<2>(s, fg, B, mmax, fract, coef, hd, phase, partial);
+    case 3: return forward_t<3>(s, fg, B, mmax, fract, coef, hd, phase, partial);
+    case 4: return forward_t<4>(s, fg, B, mmax, fract, coef, hd, phase, partial);
+    case 5: return forward_t<5>(s, fg, B, mmax, fract, coef, hd, phase, partial);
+    case 6: return forward_t<6>(s, fg, B, mmax, fract, coef, hd, phase, partial);
+    case 8: return forward_t<8>(s, fg, B, mmax, fract, coef, hd, phase, partial);
     default: return hipErrorInvalidValue;
   }
 }

@@ -58,3 +58,13 @@ def assert_phase_within_conditioning(gpu, ref, perturbed, what="phase"):
     assert ok >= min(PHI_FRAC, okp), (f"{what}: {ok:.5f} of pixels within {PHI_TOL} rad, against {okp:.5f} for the "
                                        f"perturbed FP64 run (p99.9 {np.quantile(d, 0.999):.3g} vs {np.quantile(dp, 0.999):.3g})")
     return ok, okp
+
+
+def assert_V_within_conditioning(gpu_V, ref_V, perturbed_V, what="V"):
+    """|V| within 1e-4 relative, or no further from the FP64 trajectory than the perturbed FP64 run."""
+    g = as_complex(gpu_V) if np.isrealobj(gpu_V) else gpu_V
+    b = np.abs(ref_V)
+    rel = np.abs(np.abs(g) - b) / b
+    relp = np.abs(np.abs(perturbed_V) - b) / b
+    assert rel.max() <= max(V_RTOL, relp.max()), f"{what}: max |V| rel err {rel.max():.3g} against {relp.max():.3g}"
+    return float(rel.max())

@@ -13,8 +13,8 @@ import torch
 
 import oracle
 import workloads as W
-from tests.parity import (as_complex, assert_phase, assert_phase_within_conditioning, assert_stats, assert_V, to_np,
-                          wrapped_diff)
+from tests.parity import (as_complex, assert_phase, assert_phase_within_conditioning, assert_stats, assert_V,
+                          assert_V_within_conditioning, to_np, wrapped_diff)
 
 pytestmark = pytest.mark.gpu
 
@@ -427,24 +427,25 @@ def test_max_traps_random_3d(ctx, algo):
     """HOT_MAX_TRAPS random 3D traps in the 40 x 40 x 20 um box on a 256^2 SLM: far more traps than
     resolution cells, so some fields nearly cancel (the smallest |V_m| is about 1/60 of the mean)
     and the GSW weights w <|V|>/|V_m| multiply those traps' rounding.  The random-superposition
-    mask meets the usual phase bar; after two GSW iterations the map is so ill-conditioned that the
-    FP64 oracle fed the same geometry rounded to FP32 keeps only ~95 % of pixels within 1e-3 rad,
-    so the GPU mask is held to that run.  |V| is held to 1e-4 relative on every trap whose |V_m| is
+    pass meets the usual phase bar, and |V| is held to 1e-4 relative on every trap whose |V_m| is
     at least a tenth of the mean (on the others a relative bar measures the cancellation, not the
-    arithmetic) and to 1e-5 of the mean |V| absolute on all."""
+    arithmetic) and to 1e-5 of the mean |V| absolute on all.  After two GSW iterations the map is so
+    ill-conditioned that the FP64 oracle fed the same geometry rounded to FP32 keeps only ~95 % of
+    pixels within 1e-3 rad, so the GPU mask and V are held to that run."""
     p = W.random_problem(380, 256, 256, 2048, 2)
     g = run(ctx, algo, p, 2)
     o = oracle.solve(algo, p.slm, p.xyz, p.theta0, 2)
+    gv, ov = as_complex(to_np(g.V)), o["V"]
     if algo == "rs":
         assert_phase(to_np(g.phase), o["phi"])
+        big = np.abs(ov) >= 0.1 * np.abs(ov).mean()
+        assert_V(gv[big], ov[big])
+        assert np.max(np.abs(gv - ov)) <= 1e-5 * np.abs(ov).mean()
     else:
         f32 = lambda a: a.astype(np.float32).astype(np.float64)
         pert = oracle.solve(algo, p.slm, f32(p.xyz), f32(p.theta0), 2)
         assert_phase_within_conditioning(to_np(g.phase), o["phi"], pert["phi"])
-    gv, ov = as_complex(to_np(g.V)), o["V"]
-    big = np.abs(ov) >= 0.1 * np.abs(ov).mean()
-    assert_V(gv[big], ov[big])
-    assert np.max(np.abs(gv - ov)) <= 1e-5 * np.abs(ov).mean()
+        assert_V_within_conditioning(gv, ov, pert["V"])
 
 
 def test_contexts_release_device_memory(hot):
