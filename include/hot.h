@@ -167,6 +167,24 @@ int hot_gsw(hot_ctx* ctx, const hot_slm* slm, int32_t M, const double* xyz, cons
             uint64_t seed, int32_t iters, const float* w0, float* w_out, float* theta_out,
             float* phase, float* V, hot_stats* stats);
 
+/* Allocation-free GSW, for callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc).  Same arguments, results and
+ * errors as hot_gsw, computed by the same on-the-fly kernels (whatever the context's variant) and
+ * launched eagerly; bit for bit the result of hot_gsw with the context's launch shape.  It calls
+ * no hipMalloc, hipFree or other allocating routine: every device table, state, trap sum,
+ * statistic and flag it needs lives in a fixed 1 MiB workspace per GPU (a file-scope device array
+ * whose address hot_create looks up), and its host tables go through a pinned staging buffer that
+ * hot_create allocates.  Limit: the workspace holds M traps and `iters` iterations when its six
+ * regions, 32 M (coefficients) + 32 M (state) + 64 (descriptors) + 192 M (trap sums) +
+ * 12 (iters + 1) (statistics) + 4 (flag) bytes, each rounded up to a multiple of 256, total at most
+ * 1 MiB: 2048 traps with up to 43000 iterations, 100 traps with up to 85000; larger requests fail
+ * with HOT_EINVAL before any device work.  HOT_EDEGENERATE is reported when `stats` is given.  Every call on one GPU shares that GPU's workspace, which keeps the last call's
+ * contents (the call clears what must start at zero): calls that overlap on one GPU, from any
+ * contexts or streams, race and must not be issued. */
+int hot_gsw_noalloc(hot_ctx* ctx, const hot_slm* slm, int32_t M, const double* xyz, const double* theta0,
+                    uint64_t seed, int32_t iters, const float* w0, float* w_out, float* theta_out,
+                    float* phase, float* V, hot_stats* stats);
+
 /* ---- batches of holograms sharing one SLM ------------------------------------------- */
 
 /* B independent GSW problems in one launch sequence.  Hologram b has M[b] traps; traps

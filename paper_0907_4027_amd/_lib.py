@@ -19,7 +19,7 @@ HOT_TUNE_SEP_WAVES, HOT_TUNE_SEP_CHUNK, HOT_TUNE_ROWS, HOT_TUNE_SEP_SPLIT, HOT_T
 
 # every symbol include/hot.h declares
 EXPORTS = ("hot_create", "hot_destroy", "hot_set_stream", "hot_set_variant", "hot_set_tuning", "hot_sync", "hot_check_problem",
-           "hot_rs", "hot_gs", "hot_gsw", "hot_gsw_batched", "hot_forward_V", "hot_adjoint", "hot_encode_u8", "hot_time_passes",
+           "hot_rs", "hot_gs", "hot_gsw", "hot_gsw_noalloc", "hot_gsw_batched", "hot_forward_V", "hot_adjoint", "hot_encode_u8", "hot_time_passes",
            "hot_probe_issue", "hot_probe_copy", "hot_last_error", "hot_abi_version")
 
 
@@ -66,6 +66,7 @@ def load(path: str = LIB_PATH):
         "hot_rs": ([P, S, i32, dp, dp, u64, P, P, ST], C.c_int),
         "hot_gs": ([P, S, i32, dp, dp, u64, i32, P, P, ST], C.c_int),
         "hot_gsw": ([P, S, i32, dp, dp, u64, i32, P, P, P, P, P, ST], C.c_int),
+        "hot_gsw_noalloc": ([P, S, i32, dp, dp, u64, i32, P, P, P, P, P, ST], C.c_int),
         "hot_gsw_batched": ([P, S, i32, ip, dp, dp, i32, P, P, ST], C.c_int),
         "hot_forward_V": ([P, S, i32, ip, dp, P, P], C.c_int),
         "hot_adjoint": ([P, S, i32, ip, dp, P, P, P], C.c_int),

@@ -16,7 +16,7 @@ from concurrent.futures import ThreadPoolExecutor
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
-SOURCES = [os.path.join(CSRC, f) for f in ("hot_kernels.hip", "hot_probes.hip", "hot_api.cpp")]
+SOURCES = [os.path.join(CSRC, f) for f in ("hot_kernels.hip", "hot_probes.hip", "hot_scratch.hip", "hot_api.cpp")]
 OUT = os.path.join(HERE, "libhot.so")
 OBJDIR = os.path.join(HERE, "_build")
 # packed FP32 (v_pk_*_f32) code generation stays off; the host pass warns that it does

@@ -81,6 +81,14 @@ struct hot_ctx {
   Staging ring[kRing];
   int ring_pos = 0;
   int* flag_host = nullptr;  // pinned
+  // allocation-free entry point: the device address of this GPU's fixed workspace, and a pinned
+  // host buffer of the same size (its device mapping, and an event behind its last upload), all
+  // set up by hot_create
+  void* scratch = nullptr;
+  char* na_host = nullptr;
+  char* na_dev = nullptr;
+  hipEvent_t na_ev = nullptr;
+  bool na_pending = false;
   // identity of the trap tables now on the device (skips re-upload and stored-matrix rebuilds)
   std::vector<double> key;
   bool amat_valid = false;
@@ -250,6 +258,7 @@ struct Plan {
   // one 64-bit word); every block sum and every trap's total has magnitude <= N, so no sum of the
   // scaled parts leaves +-2^30
   float acc_scale = 0.0f, acc_unscale = 0.0f;
+  HoloDesc one{};  // the first hologram's fused-kernel descriptor (passed by value when B == 1)
 };
 
 FwdGeom row_segments(int nx, int ny, int segmax) {
@@ -261,9 +270,11 @@ FwdGeom row_segments(int nx, int ny, int segmax) {
   return f;
 }
 
-// Build coefficient, state and descriptor tables on the host.
-int prepare(hot_ctx* c, const hot_slm* slm, int B, const int32_t* counts, const double* xyz, const double* theta0,
-            bool seeded, uint64_t seed, Plan& P) {
+// Build the coefficient, state and descriptor tables of a problem on the host, into coef_out [T],
+// st_out [T] and hd_out [2B] (the fused kernel's layouts, then the stand-alone trap pass's).
+int prepare_into(hot_ctx* c, const hot_slm* slm, int B, const int32_t* counts, const double* xyz,
+                 const double* theta0, bool seeded, uint64_t seed, Plan& P, TrapCoef* coef_out, TrapState* st_out,
+                 HoloDesc* hd_out) {
   P.B = B;
   P.nx = slm->nx;
   P.ny = slm->ny;
@@ -342,9 +353,6 @@ int prepare(hot_ctx* c, const hot_slm* slm, int B, const int32_t* counts, const 
   const double lf = slm->wavelength * slm->focal;
   const double ca = slm->pitch / (2.0 * lf);
   const double cg = slm->pitch * slm->pitch / (8.0 * lf * slm->focal);
-  c->h_coef.resize(P.T);
-  c->h_st.resize(P.T);
-  c->h_hd.resize(2 * (size_t)B);
   double gmax = 0.0, amax = 0.0;
   uint64_t sm = seed;
   for (int t = 0; t < P.T; ++t) {
@@ -357,7 +365,7 @@ int prepare(hot_ctx* c, const hot_slm* slm, int B, const int32_t* counts, const 
     k.g = cg * z;
     k.gf = (float)k.g;
     k.pad = 0.0f;
-    c->h_coef[t] = k;
+    coef_out[t] = k;
     gmax = std::max(gmax, std::fabs(k.g));
     amax = std::max(amax, std::fabs(k.a) + 2.0 * std::fabs(k.g) * (slm->nx - 1));
     double th;
@@ -371,7 +379,7 @@ int prepare(hot_ctx* c, const hot_slm* slm, int B, const int32_t* counts, const 
     s.theta_rev = s.theta_rad * 0.159154943091895336f;
     s.w = 1.0f;
     s.pad = 0.0f;
-    c->h_st[t] = s;
+    st_out[t] = s;
   }
   // Largest per-term argument of the direct passes, |g u^2 + a' u + C| with |a'| <= min(1/4, |a| + 2|g| Uc)
   // (a' is reduced mod 1/2), |C| < 3/2 and |u| at most the widest block of any pass in U units (the
@@ -406,13 +414,25 @@ int prepare(hot_ctx* c, const hot_slm* slm, int B, const int32_t* counts, const 
     h.off = off;
     h.tpl = P.tpl;
     layout_cost(h.m, P.fg.seg_w, Wi, P.tpl, c->tune_amax, h.g, h.a);
-    c->h_hd[b] = h;
+    hd_out[b] = h;
+    if (b == 0) P.one = h;
     h.tpl = P.tplf;
     layout_cost(h.m, P.fgf.seg_w, Wf, P.tplf, c->tune_amax, h.g, h.a);
-    c->h_hd[B + b] = h;
+    hd_out[B + b] = h;
     off += counts[b];
   }
   return HOT_OK;
+}
+
+int prepare(hot_ctx* c, const hot_slm* slm, int B, const int32_t* counts, const double* xyz, const double* theta0,
+            bool seeded, uint64_t seed, Plan& P) {
+  int64_t T = 0;
+  for (int b = 0; b < B; ++b) T += counts[b];
+  c->h_coef.resize(T);
+  c->h_st.resize(T);
+  c->h_hd.resize(2 * (size_t)B);
+  return prepare_into(c, slm, B, counts, xyz, theta0, seeded, seed, P, c->h_coef.data(), c->h_st.data(),
+                      c->h_hd.data());
 }
 
 // Device tables: coef [T], hd [2B] (fused-kernel layouts, then stand-alone trap-pass
@@ -515,7 +535,7 @@ IterArgs iter_args(hot_ctx* c, const Plan& P, float* phase, int K) {
   a.tpl = P.tpl;
   a.rows = P.rows;
   a.mmax = P.mmax;
-  if (P.B == 1) a.one = c->h_hd[0];
+  if (P.B == 1) a.one = P.one;
   a.fract = P.fract;
   a.coef = (const TrapCoef*)c->coef.p;
   a.hd = (const HoloDesc*)c->hd.p;
@@ -680,6 +700,33 @@ int check_batch(const hot_slm* slm, int32_t B, const int32_t* M, const double* x
   return HOT_OK;
 }
 
+// Layout of the allocation-free entry point's workspace for T traps and K iterations (byte
+// offsets, each region 256-byte aligned): coefficients [T], state [2][T], descriptors [2],
+// fixed-point trap sums [3][kAccRegions][T], statistics [K+1][3], the degenerate flag.  The
+// pinned staging buffer uses the same offsets.
+struct NoallocLayout {
+  size_t coef, st, hd, acc, stats, flag, total;
+};
+NoallocLayout noalloc_layout(int T, int K) {
+  auto up = [](size_t x) { return (x + 255) / 256 * 256; };
+  NoallocLayout L{};
+  size_t o = 0;
+  L.coef = o;
+  o = up(o + sizeof(TrapCoef) * (size_t)T);
+  L.st = o;
+  o = up(o + 2 * sizeof(TrapState) * (size_t)T);
+  L.hd = o;
+  o = up(o + 2 * sizeof(HoloDesc));
+  L.acc = o;
+  o = up(o + 3 * sizeof(uint64_t) * kAccRegions * (size_t)T);
+  L.stats = o;
+  o = up(o + 3 * sizeof(float) * ((size_t)K + 1));
+  L.flag = o;
+  o = up(o + sizeof(int));
+  L.total = o;
+  return L;
+}
+
 }  // namespace
 
 // ===================================================================== C ABI
@@ -724,6 +771,17 @@ int hot_create(hot_ctx** out, int device, void* stream) {
       return bail(fail(HOT_EDEVICE, "event creation failed"));
   if (hipHostMalloc((void**)&c->flag_host, sizeof(int), hipHostMallocDefault) != hipSuccess)
     return bail(fail(HOT_ENOMEM, "pinned flag allocation failed"));
+  // the allocation-free entry point's workspace: this device's copy of the fixed array (its
+  // address looked up once per device, with the device current), a pinned staging buffer of the
+  // same size and an event
+  if (scratch_address(device, &c->scratch) != hipSuccess || !c->scratch)
+    return bail(fail(HOT_EDEVICE, "the fixed device workspace has no address on device %d", device));
+  if (hipHostMalloc((void**)&c->na_host, kScratchBytes, hipHostMallocDefault) != hipSuccess)
+    return bail(fail(HOT_ENOMEM, "pinned staging allocation failed"));
+  if (hipHostGetDevicePointer((void**)&c->na_dev, c->na_host, 0) != hipSuccess || !c->na_dev)
+    return bail(fail(HOT_EDEVICE, "pinned staging buffer has no device mapping"));
+  if (hipEventCreateWithFlags(&c->na_ev, hipEventDisableTiming) != hipSuccess)
+    return bail(fail(HOT_EDEVICE, "event creation failed"));
   *c->flag_host = 0;
   int rc = ensure(c, c->flag, sizeof(int));
   if (rc) return bail(rc);
@@ -747,6 +805,11 @@ int hot_destroy(hot_ctx* c) {
     if (s.ev) (void)hipEventDestroy(s.ev);
   }
   if (c->flag_host) (void)hipHostFree(c->flag_host);
+  if (c->na_ev) {
+    if (c->na_pending) (void)hipEventSynchronize(c->na_ev);
+    (void)hipEventDestroy(c->na_ev);
+  }
+  if (c->na_host) (void)hipHostFree(c->na_host);
   if (c->own_stream) (void)hipStreamDestroy(c->own_stream);
   delete c;
   return HOT_OK;
@@ -848,6 +911,88 @@ int hot_gsw(hot_ctx* c, const hot_slm* slm, int32_t M, const double* xyz, const 
             int32_t iters, const float* w0, float* w_out, float* theta_out, float* phase, float* V,
             hot_stats* stats) {
   return single(c, slm, M, xyz, theta0, seed, kGSW, iters, w0, w_out, theta_out, phase, V, stats);
+}
+
+int hot_gsw_noalloc(hot_ctx* c, const hot_slm* slm, int32_t M, const double* xyz, const double* theta0, uint64_t seed,
+                    int32_t iters, const float* w0, float* w_out, float* theta_out, float* phase, float* V,
+                    hot_stats* stats) {
+  if (!c) return fail(HOT_EINVAL, "ctx is NULL");
+  int rc;
+  if ((rc = hot_check_problem(slm, M, xyz, iters))) return rc;
+  if (!phase || !V) return fail(HOT_EINVAL, "phase and V output pointers are required");
+  const NoallocLayout L = noalloc_layout(M, iters);
+  if (L.total > kScratchBytes)
+    return fail(HOT_EINVAL, "%d traps and %d iterations need %zu bytes of the fixed workspace, more than its %zu", M,
+                iters, L.total, kScratchBytes);
+  if (!c->scratch || !c->na_host) return fail(HOT_EDEVICE, "the fixed workspace is not set up");
+  if ((rc = set_dev(c))) return rc;
+  // the staging buffer is rewritten only once the previous call's upload from it has completed
+  if (c->na_pending) {
+    HIP_TRY(hipEventSynchronize(c->na_ev));
+    c->na_pending = false;
+  }
+  Plan P;
+  if ((rc = prepare_into(c, slm, 1, &M, xyz, theta0, theta0 == nullptr, seed, P, (TrapCoef*)(c->na_host + L.coef),
+                         (TrapState*)(c->na_host + L.st), (HoloDesc*)(c->na_host + L.hd))))
+    return rc;
+  char* base = (char*)c->scratch;
+  TrapState* st[2] = {(TrapState*)(base + L.st), (TrapState*)(base + L.st) + M};
+  unsigned long long* acc = (unsigned long long*)(base + L.acc);
+  auto acc_of = [&](int i) { return acc + (size_t)i * kAccRegions * M; };
+  int* flag = (int*)(base + L.flag);
+  float* dstats = (float*)(base + L.stats);
+  const int K = iters;
+  // tables in (coefficients, state, descriptors: one copy from the staging buffer's device
+  // mapping), then the launch sequence of hot_gsw, eagerly, with every buffer in the workspace
+  HIP_TRY(launch_copy16(c->stream, c->na_dev + L.coef, base + L.coef, (L.acc - L.coef) / 16));
+  HIP_TRY(hipEventRecord(c->na_ev, c->stream));
+  c->na_pending = true;
+  HIP_TRY(launch_fill_u32(c->stream, (unsigned*)acc_of(1), 0u, 2 * kAccRegions * M));
+  HIP_TRY(launch_fill_u32(c->stream, (unsigned*)flag, 0u, 1));
+  if (w0) HIP_TRY(launch_import_w(c->stream, w0, st[0], M));
+  IterArgs a;
+  a.fg = P.fg;
+  a.B = 1;
+  a.nt = P.nt;
+  a.q = P.q;
+  a.tpl = P.tpl;
+  a.rows = P.rows;
+  a.mmax = P.mmax;
+  a.one = P.one;
+  a.fract = P.fract;
+  a.coef = (const TrapCoef*)(base + L.coef);
+  a.hd = (const HoloDesc*)(base + L.hd);
+  a.T = M;
+  a.acc_scale = P.acc_scale;
+  a.acc_unscale = P.acc_unscale;
+  a.stats = dstats;
+  a.stat_stride = K + 1;
+  a.flag = flag;
+  for (int k = 0; k <= K; ++k) {
+    a.upd = k == 0 ? 0 : kGSW;
+    a.st_in = k == 0 ? st[0] : st[(k - 1) & 1];
+    a.st_out = st[k & 1];
+    a.acc_in = acc_of(k % 3);
+    a.acc_out = acc_of((k + 1) % 3);
+    a.acc_zero = acc_of((k + 2) % 3);
+    a.kstat = k - 1;
+    a.phase = k == K ? phase : nullptr;
+    HIP_TRY(launch_iter(c->stream, a));
+  }
+  HIP_TRY(launch_finish(c->stream, 1, M, acc_of((K + 1) % 3), P.acc_unscale, a.hd, st[K & 1], V, dstats, K, K + 1));
+  if (w_out || theta_out) HIP_TRY(launch_export_state(c->stream, st[K & 1], M, w_out, theta_out));
+  if (stats) {
+    // statistics and flag through the pinned staging buffer (its own regions, not the tables')
+    HIP_TRY(hipMemcpyAsync(c->na_host + L.stats, dstats, 3 * sizeof(float) * ((size_t)K + 1), hipMemcpyDeviceToHost,
+                           c->stream));
+    HIP_TRY(hipMemcpyAsync(c->na_host + L.flag, flag, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    c->na_pending = false;
+    memcpy(stats, c->na_host + L.stats, 3 * sizeof(float) * ((size_t)K + 1));
+    if (*(const int*)(c->na_host + L.flag))
+      return fail(HOT_EDEGENERATE, "GSW met <|V|> = 0: the phase mask sends no light to any trap");
+  }
+  return HOT_OK;
 }
 
 int hot_gsw_batched(hot_ctx* c, const hot_slm* slm, int32_t B, const int32_t* M, const double* xyz,

@@ -211,6 +211,11 @@ hipError_t launch_probe_copy(hipStream_t s, const void* src, void* dst, size_t n
 // 8-bit SLM frame encoding.
 hipError_t launch_encode_u8(hipStream_t s, const float* phase, uint8_t* frame, int64_t n);
 
+// The fixed device workspace of the allocation-free entry point (hot_scratch.hip): its size, and
+// its device address on `device` (which must be the current device).
+constexpr size_t kScratchBytes = size_t(1) << 20;
+hipError_t scratch_address(int device, void** out);
+
 // Small helpers.
 hipError_t launch_fill_u32(hipStream_t s, unsigned* p, unsigned v, int n);
 // dst <- src, n16 16-byte words (src: device memory or the device mapping of pinned host memory).

@@ -166,6 +166,25 @@ class Context:
                                            _vp(w0), _vp(w_out), _vp(th_out), _vp(phase), _vp(V), st))
         return Result(phase, V, _stats_np(st, (iters + 1, 3)), w_out, th_out)
 
+    def hot_gsw_noalloc(self, slm, xyz, theta0=None, iters: int = 10, seed: int = 0, w0=None, phase=None, V=None,
+                        stats: bool = True, state: bool = False, w_out=None, theta_out=None) -> Result:
+        """GSW through the allocation-free entry point (the library's fixed per-GPU workspace);
+        arguments and results as hot_gsw.  Output tensors are allocated here by torch when not given."""
+        s = as_slm(slm)
+        x = _host_f64(xyz, cols=3)
+        M = x.shape[0]
+        th = None if theta0 is None else _host_f64(theta0, rows=M)
+        w0 = self._dev(w0, M, "w0")
+        phase = self._dev(phase, s.nx * s.ny, "phase") if phase is not None else self._new(s.ny, s.nx)
+        V = self._dev(V, 2 * M, "V") if V is not None else self._new(M, 2)
+        w_out = self._dev(w_out, M, "w_out") if w_out is not None else (self._new(M) if state else None)
+        th_out = self._dev(theta_out, M, "theta_out") if theta_out is not None else (self._new(M) if state else None)
+        st = (hot_stats * (iters + 1))() if stats else None
+        check(self._lib, self._lib.hot_gsw_noalloc(self._ctx, C.byref(s), M, _dp(x), _dp(th), C.c_uint64(seed),
+                                                   int(iters), _vp(w0), _vp(w_out), _vp(th_out), _vp(phase), _vp(V),
+                                                   st))
+        return Result(phase, V, _stats_np(st, (iters + 1, 3)), w_out, th_out)
+
     # -- batches ---------------------------------------------------------------------
     def hot_gsw_batched(self, slm, counts, xyz, theta0, iters: int = 10, phase=None, V=None,
                         stats: bool = True) -> Result:
