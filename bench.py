@@ -26,12 +26,18 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# MI355X: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz = 3.932e13 FP32 VALU issue slots/s (non-packed).
-# sin/cos issue at half the VALU rate (2 slots).  Minimum per (pixel, trap) term of either
-# pass: 2 FMA for the phase, sin + cos (4 slots), 2 FMA/ADD to accumulate = 8 slots.
-VALU_SLOTS_PER_S = 256 * 4 * 16 * 2.4e9
-SLOTS_PER_TERM = 8
-PEAK_TERMS_PER_S = VALU_SLOTS_PER_S / SLOTS_PER_TERM
+# MI355X: 256 CUs x 4 SIMDs at the published 2.4 GHz.  The minimum work of a (pixel, trap) term of
+# either direct pass is 2 FMA for the phase, sin + cos, 2 FMA to accumulate.  Issue model: a wave64
+# FMA takes 4 shader cycles of its SIMD and a sin or cos 8, with no overlap: 32 cycles per wave of
+# 64 terms, 4.915e12 terms/s.  The probe of exactly that instruction mix (hot_probe_issue kind 2,
+# profiles/peaks_mi355x.md) runs faster than the model at high occupancy: 30.86 cycles per wave of
+# terms at 8 waves per SIMD.  The roofline takes that measured best as the peak (the stricter of the
+# two), scaled to the published clock.
+SIMDS = 256 * 4
+MODEL_CYCLES_PER_WAVE_TERM = 32.0
+PROBED_CYCLES_PER_WAVE_TERM = 30.86
+MODEL_TERMS_PER_S = SIMDS * 2.4e9 * 64 / MODEL_CYCLES_PER_WAVE_TERM
+PEAK_TERMS_PER_S = SIMDS * 2.4e9 * 64 / PROBED_CYCLES_PER_WAVE_TERM
 HBM_PEAK_GBS = 8000.0
 MFMA_F32_PEAK_TFLOPS = 157.3  # dense FP32 matrix-core peak of the MI355X
 K_SHORT = 0  # iterations of the shorter solve (the RS pass alone) whose time difference gives the per-launch duration
@@ -117,9 +123,43 @@ def measure_peaks(ctx, log):
     res["copy"] = {"bytes": nbytes, "GBs_read_plus_write": round(cp["bytes_per_s"] / 1e9, 1),
                    "ms_per_copy": round(cp["ms_per_copy"], 4), "frac_of_8TBs": round(cp["bytes_per_s"] / 8e12, 4)}
     log(f"[bench] probe copy 1 GiB: {cp['bytes_per_s'] / 1e9:.0f} GB/s read+write")
+    best = max(v["ops_per_s"] / (SIMDS * v["clock_GHz"] * 1e9) for v in res["term"].values())  # terms per SIMD cycle
     res["model"] = {"fma_cycles_per_wave_instruction": 4, "sincos_cycles_per_wave_instruction": 8,
-                    "term_cycles_per_wave": 32, "peak_terms_per_s_at_2.4GHz": PEAK_TERMS_PER_S}
+                    "term_cycles_per_wave": MODEL_CYCLES_PER_WAVE_TERM,
+                    "model_terms_per_s_at_2.4GHz": MODEL_TERMS_PER_S,
+                    "term_cycles_per_wave_measured_best": round(64.0 / best, 3),
+                    "peak_terms_per_s_used": PEAK_TERMS_PER_S,
+                    "peak_cycles_per_wave_term_used": PROBED_CYCLES_PER_WAVE_TERM}
     return res
+
+
+def onthefly_line(ctx, q, log, reps=10):
+    """One single-hologram GSW workload on the default (on-the-fly) kernels: time per solve from
+    graph replays, the iteration kernel's in-situ duration (slope against a zero-iteration solve),
+    updates/s, its fraction of the term roofline, and the figures of merit of every iteration."""
+    import torch
+    sync = torch.cuda.synchronize
+    ph = torch.empty(q.slm.ny, q.slm.nx, device="cuda")
+    Vq = torch.empty(q.m, 2, device="cuda")
+
+    def solve(k):
+        return lambda: ctx.hot_gsw(q.slm, q.xyz, q.theta0, k, phase=ph, V=Vq, stats=False)
+    solve(q.iters)()
+    solve(0)()
+    t = time_calls(solve(q.iters), reps, sync)
+    t0 = time_calls(solve(0), reps, sync)
+    per = (t - t0) / q.iters
+    terms = 2.0 * q.slm.n * q.m
+    st = ctx.hot_gsw(q.slm, q.xyz, q.theta0, q.iters, phase=ph, V=Vq, stats=True).stats
+    log(f"[bench] {q.name} on-the-fly: {t:.4f} ms per solve, iteration {per * 1e3:.2f} us in situ, "
+        f"final e={st[-1, 0]:.4f} u={st[-1, 1]:.4f} sigma={st[-1, 2]:.4f}")
+    return {"nx": q.slm.nx, "ny": q.slm.ny, "traps": q.m, "iterations": q.iters, "ms_per_solve": round(t, 4),
+            "updates_per_s": q.slm.n * q.m * q.iters / (t * 1e-3), "holograms_per_s": 1e3 / t,
+            "iteration_in_situ_us": round(per * 1e3, 3),
+            "frac_of_term_roofline": round(terms / (per * 1e-3) / PEAK_TERMS_PER_S, 4),
+            "per_iteration": {"efficiency": [round(float(v), 5) for v in st[:, 0]],
+                              "uniformity": [round(float(v), 5) for v in st[:, 1]],
+                              "sigma": [round(float(v), 5) for v in st[:, 2]]}}
 
 
 def main():
@@ -131,7 +171,7 @@ def main():
     ap.add_argument("--no-extra", action="store_true", help="skip batched / adjoint / stored comparisons")
     ap.add_argument("--no-tune", action="store_true", help="skip the autotuner's launch-shape sweep")
     ap.add_argument("--only", choices=["main", "passes", "tune", "batched", "adjoint", "stored", "interactive", "separable",
-                                       "fig7", "counters", "peaks"], default=None,
+                                       "fig7", "counters", "peaks", "workloads"], default=None,
                     help="run one section only (for profiler runs)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -244,7 +284,9 @@ def main():
         peak = PEAK_TERMS_PER_S / 1e9
         roof = {"bound": "alu", "kernel": "k_iter (GSW update + pixel pass + trap pass + trap sums, fused)",
                 "achieved": round(achieved, 1), "peak": round(peak, 1), "unit": "Gterm/s",
-                "frac": round(achieved / peak, 4), "traffic": measured_traffic("k_iter"),
+                "frac": round(achieved / peak, 4), "frac_vs_issue_model": round(achieved * 1e9 / MODEL_TERMS_PER_S, 4),
+                "peak_basis": "term-mix probe's best, 30.86 shader cycles per wave of 64 terms, at 2.4 GHz x 1024 SIMDs",
+                "traffic": measured_traffic("k_iter"),
                 "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
                 "duration": "in situ (solve-time slope over iterations)" if in_situ_ms is not None
                             else "back-to-back launches",
@@ -255,16 +297,23 @@ def main():
                 "frac_pixel_pass_alone": round(terms / (pm[2] * 1e-3) / PEAK_TERMS_PER_S, 4),
                 "frac_trap_pass_alone": round(terms / (pm[3] * 1e-3) / PEAK_TERMS_PER_S, 4)}
 
+    # ---------------------------------------------------------------- the other single-hologram workloads, on-the-fly
+    if not args.no_extra and args.only in (None, "workloads"):
+        out["workloads"] = {q.name: onthefly_line(ctx, q, log) for q in (W.c1(), W.c3())}
+
     # ---------------------------------------------------------------- batched: 64 holograms vs 64 plain launches
     if not args.no_extra and args.only in (None, "batched"):
+        from paper_0907_4027_amd import autotune
         bt = W.c4()
         T = int(bt.counts.sum())
         bph = torch.empty(bt.b, bt.slm.ny, bt.slm.nx, device="cuda")
         bV = torch.empty(T, 2, device="cuda")
         o = bt.offsets()
+        bctx = hot.Context(0)  # the batched launch with the autotuner's shape for this batch
+        tb_res = autotune.tune_batched(bctx, bt.slm, bt.counts, bt.xyz, bt.theta0, cache=None)
 
         def batched():
-            ctx.hot_gsw_batched(bt.slm, bt.counts, bt.xyz, bt.theta0, bt.iters, phase=bph, V=bV, stats=False)
+            bctx.hot_gsw_batched(bt.slm, bt.counts, bt.xyz, bt.theta0, bt.iters, phase=bph, V=bV, stats=False)
 
         def sequential():
             for b in range(bt.b):
@@ -272,20 +321,31 @@ def main():
                             phase=bph[b], V=bV[o[b]:o[b + 1]], stats=False)
 
         batched()
-        sequential()
+        sequential()  # every hologram's captured graph is now cached (one per output buffer)
+        sync()
         tb = time_calls(batched, 3, sync)
         ts = time_calls(sequential, 2, sync)
+        tbw = time_wall(batched, 3, sync)
+        tsw = time_wall(sequential, 2, sync)
         upd = bt.slm.n * T * bt.iters
         # whole batched solve (31 launches of the fused kernel plus the per-solve kernels) against
         # the issue-slot roofline: 2 terms per pixel-trap update, plus the initial pass
         terms = 2.0 * bt.slm.n * T * (bt.iters + 1)
+        table = tb_res["table"]
         out["batched"] = {"workload": f"{bt.name}: 64 x 512^2, M in [4,256] (sum {T}), 30 iterations",
                           "ms": round(tb, 3), "updates_per_s": upd / (tb * 1e-3), "holograms_per_s": bt.b / (tb * 1e-3),
                           "plain_ms": round(ts, 3), "plain_updates_per_s": upd / (ts * 1e-3),
                           "speedup_vs_plain": round(ts / tb, 3),
+                          "timing": "device: HIP events on the stream around the calls; wall: host clock with a final "
+                                    "synchronisation; the plain form replays each hologram's cached graph",
+                          "wall_ms": round(tbw, 3), "plain_wall_ms": round(tsw, 3),
+                          "autotuned_shape": tb_res["knobs"],
+                          "autotune": {"configurations": len(table), "best_ms_2_iterations": table[0]["ms_per_solve"],
+                                       "worst_ms_2_iterations": table[-1]["ms_per_solve"]},
                           "frac_of_term_roofline": round(terms / (tb * 1e-3) / PEAK_TERMS_PER_S, 4)}
-        log(f"[bench] batched {tb:.3f} ms vs 64 plain {ts:.3f} ms; whole batched solve at "
-            f"{out['batched']['frac_of_term_roofline']:.3f} of the term roofline")
+        bctx.close()
+        log(f"[bench] batched (autotuned {tb_res['knobs']}) {tb:.3f} ms vs 64 plain {ts:.3f} ms (wall {tbw:.3f} vs "
+            f"{tsw:.3f}); whole batched solve at {out['batched']['frac_of_term_roofline']:.3f} of the term roofline")
 
     # ---------------------------------------------------------------- adjoint: 8 x (forward + adjoint) per Adam step
     if not args.no_extra and args.only in (None, "adjoint"):
@@ -308,24 +368,38 @@ def main():
 
         batched_fa()
         plain_fa()
-        # wall clock with a final synchronisation, best of three runs of 10 steps: HIP event pairs
-        # around the plain form (16 calls that each upload a new hologram's tables) were seen to
-        # report many times the time the work took, and single runs of it vary with transient
-        # stalls of the host runtime, so both forms are timed the same way from the host
+        # both forms by wall clock with a final synchronisation (best of three runs of 10 steps) and
+        # by HIP events on the stream (device time, including any gaps the host leaves); the plain
+        # form is 16 calls that each upload a hologram's trap tables
         tb = min(time_wall(batched_fa, 10, sync) for _ in range(3))
         tp = min(time_wall(plain_fa, 10, sync) for _ in range(3))
+        tbe = time_calls(batched_fa, 10, sync)
+        tpe = time_calls(plain_fa, 10, sync)
         sync()
         h0 = time.perf_counter()
         for _ in range(10):
             plain_fa()
         host_ms = (time.perf_counter() - h0) / 10 * 1e3
         sync()
+        # the workload's Adam step (lr 0.05): batched forward, loss, adjoint backward, Adam update
+        phase0 = (torch.rand(bt.b, bt.slm.ny, bt.slm.nx, device="cuda") * (2 * math.pi)).contiguous()
+        hot.optimize_phase(ctx, bt.slm, bt.counts, bt.xyz, phase0, steps=3, lr=0.05)
+        sync()
+        a0 = time.perf_counter()
+        _, losses = hot.optimize_phase(ctx, bt.slm, bt.counts, bt.xyz, phase0, steps=50, lr=0.05)
+        sync()
+        adam_ms = (time.perf_counter() - a0) / 50 * 1e3
         upd = bt.slm.n * T
         out["adjoint"] = {"workload": f"{bt.name}: forward V + adjoint dL/dphi, 8 x 512^2 x 64 traps",
                           "ms": round(tb, 4), "updates_per_s": upd / (tb * 1e-3), "plain_ms": round(tp, 4),
                           "plain_updates_per_s": upd / (tp * 1e-3), "speedup_vs_plain": round(tp / tb, 3),
-                          "plain_host_enqueue_ms": round(host_ms, 4)}
-        log(f"[bench] forward+adjoint batched {tb:.4f} ms vs plain {tp:.4f} ms (plain host enqueue {host_ms:.4f} ms)")
+                          "device_ms": round(tbe, 4), "plain_device_ms": round(tpe, 4),
+                          "speedup_vs_plain_device": round(tpe / tbe, 3),
+                          "plain_host_enqueue_ms": round(host_ms, 4),
+                          "adam_step_ms": round(adam_ms, 4),
+                          "adam_loss_first_last_of_50": [round(float(losses[0]), 4), round(float(losses[-1]), 4)]}
+        log(f"[bench] forward+adjoint batched {tb:.4f} ms vs plain {tp:.4f} ms wall, {tbe:.4f} vs {tpe:.4f} ms device "
+            f"(plain host enqueue {host_ms:.4f} ms); Adam step {adam_ms:.3f} ms")
 
     # ---------------------------------------------------------------- stored exp(i Delta) variant (HBM-bound)
     if not args.no_extra and args.only in (None, "stored"):

@@ -1,5 +1,10 @@
 """Autotuner for the launch-shape knobs of the C ABI (``hot_set_tuning``).
 
+Two entry points: ``tune``/``sweep`` for one hologram (back-to-back launches of the fused
+iteration kernel through ``hot_time_passes``) and ``tune_batched``/``sweep_batched`` for a batch of
+holograms with uneven trap counts (short batched solves timed with HIP events on the context's
+stream).
+
 For one problem shape it times every candidate combination of
 
     pixels_per_lane  (pixel pass: 1 or 2 pixels per lane, i.e. 512- or 256-thread rows on 512-wide rows)
@@ -85,6 +90,78 @@ def tune(ctx: Context, slm, xyz, theta0, cache: Optional[str] = DEFAULT_CACHE, r
             with open(cache, "w") as f:
                 json.dump(db, f, indent=1, sort_keys=True)
     knobs = {k: db[key][k] for k in ("pixels_per_lane", "segment", "traps_per_lane", "rows") if k in db[key]}
+    if apply:
+        ctx.set_tuning(**knobs)
+    return {"key": key, "knobs": knobs, "table": table}
+
+
+BATCH_CANDIDATES = {
+    "traps_per_lane": (0, 2, 3, 4, 5, 6, 8),
+    "rows": (1, 2),
+    "pixels_per_lane": (0, 1),
+}
+
+
+def batch_key(ctx: Context, slm, counts, variant: str = "onthefly") -> str:
+    """Cache key of a batch: architecture, grid, batch size and the trap-count distribution
+    (quartiles bucketed to powers of two)."""
+    arch = torch.cuda.get_device_properties(ctx.device).gcnArchName.split(":")[0]
+    import numpy as np
+    q = [_bucket(int(v)) for v in np.quantile(np.asarray(counts), (0.0, 0.25, 0.5, 0.75, 1.0))]
+    return f"{arch}/{variant}/batched/{int(slm.nx)}x{int(slm.ny)}/B{len(counts)}/M" + "-".join(map(str, q))
+
+
+def sweep_batched(ctx: Context, slm, counts, xyz, theta0, iters: int = 2, reps: int = 3,
+                  candidates: Optional[dict] = None) -> list:
+    """Time hot_gsw_batched (a short solve of `iters` iterations, graph-replayed) for every knob
+    combination; rows sorted by device milliseconds per solve."""
+    import numpy as np
+    cand = candidates or BATCH_CANDIDATES
+    cnt = np.asarray(counts, dtype=np.int32)
+    B, T = len(cnt), int(cnt.sum())
+    phase = torch.empty(B, int(slm.ny), int(slm.nx), device=ctx.device)
+    V = torch.empty(T, 2, device=ctx.device)
+    rows = []
+    for tpl, nr, q in itertools.product(cand["traps_per_lane"], cand["rows"], cand["pixels_per_lane"]):
+        try:
+            ctx.set_tuning(traps_per_lane=tpl, rows=nr, pixels_per_lane=q)
+            run = lambda: ctx.hot_gsw_batched(slm, cnt, xyz, theta0, iters, phase=phase, V=V, stats=False)
+            run()
+            torch.cuda.synchronize(ctx.device)
+        except Exception:  # a shape the library refuses for this batch (e.g. two rows on 512-thread rows)
+            continue
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            run()
+        e1.record()
+        torch.cuda.synchronize(ctx.device)
+        rows.append({"traps_per_lane": tpl, "rows": nr, "pixels_per_lane": q,
+                     "ms_per_solve": round(e0.elapsed_time(e1) / reps, 4)})
+    ctx.set_tuning()
+    rows.sort(key=lambda r: r["ms_per_solve"])
+    return rows
+
+
+def tune_batched(ctx: Context, slm, counts, xyz, theta0, cache: Optional[str] = DEFAULT_CACHE, iters: int = 2,
+                 reps: int = 3, apply: bool = True) -> dict:
+    """Best knobs for this batch shape (cached like ``tune``); applied to ctx when `apply`."""
+    key = batch_key(ctx, slm, counts)
+    db = {}
+    if cache and os.path.exists(cache):
+        with open(cache) as f:
+            db = json.load(f)
+    table = None
+    if key not in db:
+        table = sweep_batched(ctx, slm, counts, xyz, theta0, iters=iters, reps=reps)
+        best = table[0]
+        db[key] = {k: best[k] for k in ("traps_per_lane", "rows", "pixels_per_lane")} | \
+                  {"ms_per_solve": best["ms_per_solve"]}
+        if cache:
+            os.makedirs(os.path.dirname(cache), exist_ok=True)
+            with open(cache, "w") as f:
+                json.dump(db, f, indent=1, sort_keys=True)
+    knobs = {k: db[key][k] for k in ("traps_per_lane", "rows", "pixels_per_lane")}
     if apply:
         ctx.set_tuning(**knobs)
     return {"key": key, "knobs": knobs, "table": table}

@@ -54,6 +54,9 @@ struct Staging {
 };
 
 constexpr int kRing = 8;
+// captured launch sequences kept per context (least recently used dropped first): enough for a
+// batch of holograms solved one by one into their own output buffers
+constexpr int kGraphCache = 128;
 constexpr double kPi = 3.14159265358979323846;
 
 }  // namespace
@@ -657,7 +660,7 @@ int solve(hot_ctx* c, const hot_slm* slm, int B, const int32_t* counts, const do
         (void)hipGetLastError();
         c->use_graphs = 0;
       } else {
-        if (c->graphs.size() >= 8) {
+        if (c->graphs.size() >= (size_t)kGraphCache) {
           auto lru = std::min_element(c->graphs.begin(), c->graphs.end(),
                                       [](const auto& x, const auto& y) { return x.last_use < y.last_use; });
           (void)hipGraphExecDestroy(lru->exec);

@@ -1050,9 +1050,10 @@ __device__ __forceinline__ void trap_tiles(const float2* xc, const float2* yc, i
 //   a fixed order (first half + second half), so both waves hold the same S, and the phase is
 //   written by the first.  Twice the waves per SIMD, the same work.
 // Grid (ceil(nx / 16 W), ceil(ny / 16), B), W KH waves per block; sc = traps per super-chunk (a
-// multiple of 16); dynamic LDS sep_lds_bytes(W, sc, Mmax, KH).
+// multiple of 16); dynamic LDS sep_lds_bytes(W, sc, Mmax, KH).  At least two waves per SIMD
+// (<= 256 registers per wave, AGPRs included): on large grids two blocks then share a compute unit.
 template <int W, int MODE, int KH>
-__global__ void __launch_bounds__(W * KH * 64)
+__global__ void __launch_bounds__(W * KH * 64, 2)
 k_sep(const TrapCoef* __restrict__ coef, const HoloDesc* __restrict__ hd, const TrapState* __restrict__ st_in,
       TrapState* __restrict__ st_out, const float* __restrict__ vin, float* __restrict__ stats, int kstat,
       int stat_stride, int upd, int* __restrict__ flag, int nx, int ny, float inv_n, int sc,
@@ -1087,39 +1088,57 @@ k_sep(const TrapCoef* __restrict__ coef, const HoloDesc* __restrict__ hd, const 
   for (int v = 0; v < 4; ++v) in[v] = r < ny && c0 + 4 * g + v < nx;
   float er[4], ei[4];
 
-  // tables of traps [k0, k0 + n) into LDS: lane j keeps trap k0 + j's coefficients in registers
-  // while its wave walks the block's columns wave, wave + NW, ... (tables_x) or rows wave,
-  // wave + NW, ... (tables_y).  Each argument, g U^2 + a U or g V^2 + b V, is formed in FP64
-  // (exact to ~1e-16 rev for these integer U, V) and reduced to one period before the FP32
-  // sin/cos.  Columns past nx and rows past ny take the coordinates of the last column and row
-  // (finite entries; such pixels have E = 0), and traps past M are left as the formula gives
-  // them (c_m = 0, partials never written), so none of them reach V or the phase.
+  // tables of traps [k0, k0 + n) into LDS.  Eq. 2's factors are formed about a reference column
+  // (row) of each group of 16: for the group's columns c = c_t + i, i in [-8, 8) (c_t = the group's
+  // first column + 8),
+  //   X_m(c) = e^{i 2pi (K_t + s_t i + 4 g i^2)},  K_t = g U_t^2 + a U_t (mod 1),  s_t = 4 g U_t + 2 a (mod 1)
+  // with U_t = 2 c_t - (nx - 1) (exact for integer i); K_t and s_t are formed in FP64 (exact to
+  // ~1e-16 rev) once per trap and group, and each entry's argument, under 5 rev, in FP32.  Rows
+  // likewise, one group per block.  Lane j keeps trap k0 + j's group constants in registers while
+  // its wave fills its share of the group's entries: wave w takes columns 16 (w % W) + (w / W) 16 / KH
+  // + [0, 16 / KH) (tables_x) or rows w, w + NW, ... (tables_y).  Columns past nx and rows past ny
+  // get the formula's values (finite, small arguments; such pixels have E = 0), and traps past M
+  // are left as the formula gives them (c_m = 0, partials never written), so none of them reach
+  // V or the phase.
   static_assert(16 % NW == 0, "rows of a block split evenly over its waves");
-  auto factor = [](double g, double lin, double X) {
-    const double d = __builtin_fma(g, X * X, lin * X);
-    const float t = (float)(d - __builtin_floor(d));
+  auto group_ref = [](double g, double lin, double X) {  // (K, s) about integer coordinate X
+    const double k = __builtin_fma(g, X * X, lin * X);
+    double sl = __builtin_fma(4.0 * g, X, 2.0 * lin);
+    sl -= __builtin_rint(sl);
+    return make_float2((float)(k - __builtin_floor(k)), (float)sl);
+  };
+  auto factor = [](float2 ks, float q, int i) {
+    const float fi = (float)i;
+    const float t = __builtin_fmaf(q, fi * fi, __builtin_fmaf(ks.y, fi, ks.x));
     return make_float2(__builtin_amdgcn_cosf(t), __builtin_amdgcn_sinf(t));
   };
+  const int xg = wave % W, xsub = wave / W;  // the column group this wave fills, and its share of it
   auto tables_x = [&](int k0, int n) {
+    const double Ut = (double)(2 * (cb + 16 * xg + 8) - (nx - 1));
     for (int j = lane; j < n; j += 64) {
       const TrapCoef k = cf[k0 + j];
+      const float2 ks = group_ref(k.g, k.a, Ut);
+      const float q = (float)(4.0 * k.g);
 #pragma unroll
       for (int i = 0; i < 16 / KH; ++i) {
-        const double U = (double)(2 * min(cb + wave + i * NW, nx - 1) - (nx - 1));
-        xt[(wave + i * NW) * XS + j] = factor(k.g, k.a, U);
+        const int col = 16 * xg + xsub * (16 / KH) + i;
+        xt[col * XS + j] = factor(ks, q, col - 16 * xg - 8);
       }
     }
   };
   auto tables_y = [&](int k0, int n, bool weighted) {
+    const double Vt = (double)(2 * (row0 + 8) - (ny - 1));
     for (int j = lane; j < n; j += 64) {
       const TrapCoef k = cf[k0 + j];
+      const float2 ks = group_ref(k.g, k.b, Vt);
+      const float q = (float)(4.0 * k.g);
       const float2 w = weighted ? cw[k0 + j] : make_float2(0.0f, 0.0f);
 #pragma unroll
       for (int i = 0; i < 16 / NW; ++i) {
-        const double V = (double)(2 * min(row0 + wave + i * NW, ny - 1) - (ny - 1));
-        const float2 v = factor(k.g, k.b, V);
-        yt[(wave + i * NW) * XS + j] = v;
-        if (weighted) ywt[(wave + i * NW) * XS + j] = cmul(w, v);
+        const int row = wave + i * NW;
+        const float2 v = factor(ks, q, row - 8);
+        yt[row * XS + j] = v;
+        if (weighted) ywt[row * XS + j] = cmul(w, v);
       }
     }
   };
