@@ -214,11 +214,21 @@ def main():
         with hot.Context(0) as tctx:
             tr = autotune.tune(tctx, p.slm, p.xyz, p.theta0, cache=None, reps=20, apply=False)
             pd = tctx.hot_time_passes(p.slm, p.xyz, p.theta0, reps=20)
+            # the paper's Table 1 axes on its SR grid (768 x 768), 100 traps in the workloads' box
+            t1slm = W.Slm(768, 768)
+            t1 = autotune.table1_sweep(tctx, t1slm, p.xyz, p.theta0, reps=20)
         table = tr["table"]
         default = {"iteration_us": round(float(pd[0]) * 1e3, 3), "reduce_us": round(float(pd[1]) * 1e3, 3)}
         tuning = {"best_knobs": tr["knobs"], "best": table[0], "library_default": default, "worst": table[-1],
                   "configurations": len(table),
-                  "best_vs_default": round(default["iteration_us"] / table[0]["iteration_us"], 4)}
+                  "best_vs_default": round(default["iteration_us"] / table[0]["iteration_us"], 4),
+                  "table1": {"workload": "random-superposition pixel pass, 768 x 768 SLM, 100 traps (the paper's "
+                                         "Table 1 axes: record placement, pixel mapping, block size)",
+                             "rows": t1,
+                             "paper_context": "GTX 260, 768^2: 0.35 ms per trap with all rules, 1.22 without shared-"
+                                              "memory records (other hardware)"}}
+        log("[bench] table 1 axes: " + "  ".join(f"{r['placement']}/{r['mapping']}/{r['block']}: {r['ms_per_pass'] * 1e3:.1f}us"
+                                                  for r in t1))
         log(f"[bench] autotune sweep: best {tr['knobs']} {table[0]['iteration_us']} us, library default "
             f"{default['iteration_us']} us, worst {table[-1]['iteration_us']} us over {len(table)} shapes")
     if args.only in (None, "main"):

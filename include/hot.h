@@ -234,6 +234,21 @@ int hot_encode_u8(hot_ctx* ctx, int64_t n, const float* phase, uint8_t* frame);
 int hot_time_passes(hot_ctx* ctx, const hot_slm* slm, int32_t M, const double* xyz, const double* theta0,
                     int32_t reps, float* phase, float* V, float* ms);
 
+/* Ablation of the pixel pass's design choices (the paper's rules of Section 2, measured in its
+ * Table 1, Section 4), for the random-superposition pass: Eq. 3 with w_m = 1 and theta0 (host, M
+ * radians), written to `phase` (device, nx*ny floats).  `placement` says where each thread finds
+ * the per-trap records: HOT_REC_LDS (staged in LDS, read as broadcasts), HOT_REC_SCALAR (read from
+ * global memory through the scalar cache, one load per wave), HOT_REC_GLOBAL (read from global
+ * memory by every lane); `mapping` how pixels map to a block of `block` threads (64 or 256):
+ * HOT_MAP_LINEAR (consecutive pixels of a row) or HOT_MAP_SQUARE (a square tile, 8x8 or 16x16:
+ * one more FMA per term, as the row varies inside a block).  Records are formed once per block in
+ * FP64 (a small table the context holds), then the pass is launched `reps` times back to back;
+ * ms[0] gets the mean device milliseconds per launch.  Synchronises the context's stream. */
+enum hot_record_placement { HOT_REC_LDS = 0, HOT_REC_SCALAR = 1, HOT_REC_GLOBAL = 2 };
+enum hot_pixel_mapping { HOT_MAP_LINEAR = 0, HOT_MAP_SQUARE = 1 };
+int hot_pixel_pass_variant(hot_ctx* ctx, const hot_slm* slm, int32_t M, const double* xyz, const double* theta0,
+                           int placement, int mapping, int block, int32_t reps, float* phase, float* ms);
+
 /* Measurement aid: issue rate of the FP32 vector pipes that bound the direct passes.  Launches
  * one block of 4 * waves_per_simd waves per compute unit (waves_per_simd 1, 2, 4 or 8), each wave
  * running `reps` repetitions (1..2^24) of an unrolled instruction stream of one kind:

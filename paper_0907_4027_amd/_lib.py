@@ -16,10 +16,12 @@ HOT_ONTHEFLY, HOT_STORED, HOT_SEPARABLE = 0, 1, 2
 HOT_MAX_TRAPS, HOT_MAX_SIDE, HOT_MAX_BATCH = 2048, 4096, 4096
 HOT_TUNE_PIXELS_PER_LANE, HOT_TUNE_TRAPS_PER_LANE, HOT_TUNE_SEGMENT, HOT_TUNE_SLICES, HOT_TUNE_GRAPHS = 1, 2, 3, 4, 5
 HOT_TUNE_SEP_WAVES, HOT_TUNE_SEP_CHUNK, HOT_TUNE_ROWS, HOT_TUNE_SEP_SPLIT, HOT_TUNE_FRACT = 6, 7, 8, 9, 10
+HOT_REC_LDS, HOT_REC_SCALAR, HOT_REC_GLOBAL = 0, 1, 2
+HOT_MAP_LINEAR, HOT_MAP_SQUARE = 0, 1
 
 # every symbol include/hot.h declares
 EXPORTS = ("hot_create", "hot_destroy", "hot_set_stream", "hot_set_variant", "hot_set_tuning", "hot_sync", "hot_check_problem",
-           "hot_rs", "hot_gs", "hot_gsw", "hot_gsw_noalloc", "hot_gsw_batched", "hot_forward_V", "hot_adjoint", "hot_encode_u8", "hot_time_passes",
+           "hot_rs", "hot_gs", "hot_gsw", "hot_gsw_noalloc", "hot_gsw_batched", "hot_forward_V", "hot_adjoint", "hot_encode_u8", "hot_time_passes", "hot_pixel_pass_variant",
            "hot_probe_issue", "hot_probe_copy", "hot_last_error", "hot_abi_version")
 
 
@@ -72,6 +74,8 @@ def load(path: str = LIB_PATH):
         "hot_adjoint": ([P, S, i32, ip, dp, P, P, P], C.c_int),
         "hot_encode_u8": ([P, C.c_int64, P, P], C.c_int),
         "hot_time_passes": ([P, S, i32, dp, dp, i32, P, P, C.POINTER(C.c_float)], C.c_int),
+        "hot_pixel_pass_variant": ([P, S, i32, dp, dp, C.c_int, C.c_int, C.c_int, i32, P, C.POINTER(C.c_float)],
+                                   C.c_int),
         "hot_probe_issue": ([P, C.c_int, C.c_int, C.c_int64, dp], C.c_int),
         "hot_probe_copy": ([P, P, P, C.c_int64, C.c_int, dp], C.c_int),
         "hot_last_error": ([], C.c_char_p),

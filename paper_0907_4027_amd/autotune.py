@@ -165,3 +165,21 @@ def tune_batched(ctx: Context, slm, counts, xyz, theta0, cache: Optional[str] = 
     if apply:
         ctx.set_tuning(**knobs)
     return {"key": key, "knobs": knobs, "table": table}
+
+
+TABLE1_VARIANTS = [(pl, mp, bs) for pl in ("lds", "scalar", "global") for mp in ("linear", "square") for bs in (64, 256)]
+
+
+def table1_sweep(ctx: Context, slm, xyz, theta0, reps: int = 20) -> list:
+    """The MI355X analogue of the paper's Table 1 (Section 4): the random-superposition pixel pass
+    with the trap records in LDS, read by scalar loads or read by every lane from global memory,
+    pixels in row segments or square tiles, blocks of 64 or 256 pixels; rows sorted by time, with
+    the paper's unit (ms per trap) and terms per second."""
+    n, m = int(slm.nx) * int(slm.ny), len(xyz)
+    rows = []
+    for pl, mp, bs in TABLE1_VARIANTS:
+        _, ms = ctx.hot_pixel_pass_variant(slm, xyz, theta0, placement=pl, mapping=mp, block=bs, reps=reps)
+        rows.append({"placement": pl, "mapping": mp, "block": bs, "ms_per_pass": round(ms, 5),
+                     "ms_per_trap": round(ms / m, 6), "terms_per_s": n * m / (ms * 1e-3)})
+    rows.sort(key=lambda r: r["ms_per_pass"])
+    return rows

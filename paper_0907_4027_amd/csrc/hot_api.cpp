@@ -80,6 +80,7 @@ struct hot_ctx {
   uint64_t graph_clock = 0;
   DevBuf coef, st, hd, partial, stats, flag, amat, efield;
   DevBuf probe;  // micro-benchmark sink and clock stamps
+  DevBuf abl;    // per-block records of the pixel-pass ablation
   DevBuf acc;  // fused paths: 3 rotating buffers of fixed-point trap sums [kAccRegions][T] u64 (re + 2^32 im)
   Staging ring[kRing];
   int ring_pos = 0;
@@ -800,7 +801,7 @@ int hot_destroy(hot_ctx* c) {
   (void)hipStreamSynchronize(c->stream);
   for (auto& g : c->graphs) (void)hipGraphExecDestroy(g.exec);
   for (DevBuf* b : {&c->coef, &c->st, &c->hd, &c->partial, &c->stats, &c->flag, &c->amat, &c->efield, &c->acc,
-                    &c->probe})
+                    &c->probe, &c->abl})
     if (b->p) (void)hipFree(b->p);
   for (auto& s : c->ring) {
     if (s.pending && s.ev) (void)hipEventSynchronize(s.ev);
@@ -1203,6 +1204,46 @@ int hot_time_passes(hot_ctx* c, const hot_slm* slm, int32_t M, const double* xyz
   } while (0);
   for (auto& e : ev) (void)hipEventDestroy(e);
   return out;
+}
+
+int hot_pixel_pass_variant(hot_ctx* c, const hot_slm* slm, int32_t M, const double* xyz, const double* theta0,
+                           int placement, int mapping, int block, int32_t reps, float* phase, float* ms) {
+  if (!c) return fail(HOT_EINVAL, "ctx is NULL");
+  int rc;
+  if ((rc = hot_check_problem(slm, M, xyz, 0))) return rc;
+  if (!theta0 || !phase || !ms) return fail(HOT_EINVAL, "theta0, phase and ms are required");
+  if (placement < HOT_REC_LDS || placement > HOT_REC_GLOBAL) return fail(HOT_EINVAL, "unknown placement %d", placement);
+  if (mapping != HOT_MAP_LINEAR && mapping != HOT_MAP_SQUARE) return fail(HOT_EINVAL, "unknown mapping %d", mapping);
+  if (block != 64 && block != 256) return fail(HOT_EINVAL, "block must be 64 or 256 pixels");
+  if (reps < 1) return fail(HOT_EINVAL, "reps = %d < 1", reps);
+  if ((rc = set_dev(c))) return rc;
+  Plan P;
+  if ((rc = prepare(c, slm, 1, &M, xyz, theta0, false, 0, P))) return rc;
+  if ((rc = upload_tables(c, slm, P, xyz, &M))) return rc;
+  const int nb = abl_blocks(mapping, block, slm->nx, slm->ny);
+  if ((rc = ensure(c, c->abl, sizeof(float4) * (size_t)nb * M))) return rc;
+  float4* records = (float4*)c->abl.p;
+  HIP_TRY(launch_abl_records(c->stream, mapping, block, slm->nx, slm->ny, M, (const TrapCoef*)c->coef.p,
+                             (const TrapState*)c->st.p, records));
+  HIP_TRY(launch_abl_pixel(c->stream, placement, mapping, block, slm->nx, slm->ny, M, records, phase));
+  hipEvent_t e0, e1;
+  HIP_TRY(hipEventCreate(&e0));
+  HIP_TRY(hipEventCreate(&e1));
+  int res = HOT_OK;
+  if (hipEventRecord(e0, c->stream) != hipSuccess) res = fail(HOT_EDEVICE, "event record failed");
+  for (int i = 0; i < reps && res == HOT_OK; ++i)
+    if (launch_abl_pixel(c->stream, placement, mapping, block, slm->nx, slm->ny, M, records, phase) != hipSuccess)
+      res = fail(HOT_EDEVICE, "launch failed");
+  if (res == HOT_OK && (hipEventRecord(e1, c->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess))
+    res = fail(HOT_EDEVICE, "event timing failed");
+  if (res == HOT_OK) {
+    float t = 0.0f;
+    (void)hipEventElapsedTime(&t, e0, e1);
+    ms[0] = t / (float)reps;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  return res;
 }
 
 int hot_probe_issue(hot_ctx* c, int kind, int waves_per_simd, int64_t reps, double* out) {

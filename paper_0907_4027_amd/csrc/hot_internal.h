@@ -208,6 +208,14 @@ hipError_t launch_probe(hipStream_t s, int kind, int blocks, int threads, long l
 // Device copy of n16 16-byte words on `blocks` blocks of 256 threads.
 hipError_t launch_probe_copy(hipStream_t s, const void* src, void* dst, size_t n16, int blocks);
 
+// Table 1 ablation of the random-superposition pixel pass (placement 0 LDS, 1 scalar loads, 2 global
+// per-lane loads; mapping 0 linear row segments, 1 square tiles; bs = 64 or 256 pixels per block).
+int abl_blocks(int mapping, int bs, int nx, int ny);
+hipError_t launch_abl_records(hipStream_t s, int mapping, int bs, int nx, int ny, int M, const TrapCoef* coef,
+                              const TrapState* st, float4* records);
+hipError_t launch_abl_pixel(hipStream_t s, int placement, int mapping, int bs, int nx, int ny, int M,
+                            const float4* records, float* phase);
+
 // 8-bit SLM frame encoding.
 hipError_t launch_encode_u8(hipStream_t s, const float* phase, uint8_t* frame, int64_t n);
 

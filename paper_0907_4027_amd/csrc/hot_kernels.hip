@@ -1331,6 +1331,114 @@ k_sep(const TrapCoef* __restrict__ coef, const HoloDesc* __restrict__ hd, const 
   }
 }
 
+// ------------------------------------------------------------------ Table 1 ablation: the pixel pass of random superposition
+//
+// The paper's design rules for its pixel-pass kernel (Section 2; Table 1, Section 4) vary where a
+// thread finds the trap parameters and how pixels map to threads.  These kernels time the same
+// choices on gfx950 for the random-superposition pass (Eq. 3 with w_m = 1):
+//   placement  LDS (records staged into shared memory, read as broadcasts), SCALAR (read from global
+//              memory through the scalar cache: one load per wave), GLOBAL (read from global memory by
+//              every lane: vector loads of one address)
+//   mapping    LINEAR (a block is BS consecutive pixels of a row) or SQUARE (a block is a sqrt(BS) x
+//              sqrt(BS) tile of pixels)
+// Records are formed once per block by k_abl_records, in FP64 about the block's centre: LINEAR
+// {a', g, K + theta_rev, 0} with t = g u^2 + a' u + C (2 FMA), SQUARE {a', b', g, K + theta_rev} with
+// t = g (u^2 + v^2) + a' u + b' v + C (3 FMA: the row is no longer constant within a block).
+enum { kAblLds = 0, kAblScalar = 1, kAblGlobal = 2 };
+enum { kAblLinear = 0, kAblSquare = 1 };
+
+template <int MAP>
+__device__ __forceinline__ void abl_block(int blk, int nx, int ny, int BS, int& c0, int& r0, int& cw, int& rh) {
+  if constexpr (MAP == kAblLinear) {
+    const int nxb = (nx + BS - 1) / BS;
+    r0 = blk / nxb;
+    c0 = (blk - r0 * nxb) * BS;
+    cw = BS;
+    rh = 1;
+  } else {
+    const int side = BS == 64 ? 8 : 16;
+    const int nxb = (nx + side - 1) / side;
+    r0 = (blk / nxb) * side;
+    c0 = (blk - blk / nxb * nxb) * side;
+    cw = side;
+    rh = side;
+  }
+}
+
+// One block per pixel block, threads over traps: records[blk][m].
+template <int MAP>
+__global__ void __launch_bounds__(256)
+k_abl_records(const TrapCoef* __restrict__ coef, const TrapState* __restrict__ st, int M, int nx, int ny, int BS,
+              float4* __restrict__ records) {
+  const int blk = blockIdx.x;
+  int c0, r0, cw, rh;
+  abl_block<MAP>(blk, nx, ny, BS, c0, r0, cw, rh);
+  const int cc = centre_col(c0, min(nx - c0, cw)), rc = r0 + (max(min(ny - r0, rh), 1) - 1) / 2;
+  const double Uc = (double)(2 * cc - (nx - 1)), Vc = (double)(2 * rc - (ny - 1));
+  for (int m = threadIdx.x; m < M; m += 256) {
+    const TrapCoef c = coef[m];
+    const float k = block_const(c, Uc, Vc) + st[m].theta_rev;
+    float4 r;
+    if constexpr (MAP == kAblLinear) {
+      r = make_float4(block_slope(c, Uc), c.gf, k, 0.0f);
+    } else {
+      double bp = __builtin_fma(2.0 * c.g, Vc, c.b);  // b' = b + 2 g Vc, mod 1/2 (v is even)
+      bp -= 0.5 * __builtin_rint(2.0 * bp);
+      r = make_float4(block_slope(c, Uc), (float)bp, c.gf, k);
+    }
+    records[(size_t)blk * M + m] = r;
+  }
+}
+
+template <int PLACE, int MAP, int BS>
+__global__ void __launch_bounds__(BS)
+k_abl_pixel(const float4* __restrict__ records, int M, int nx, int ny, float* __restrict__ phase) {
+  __shared__ float4 lrec[PLACE == kAblLds ? kMaxTraps : 1];
+  const int blk = blockIdx.x;
+  int c0, r0, cw, rh;
+  abl_block<MAP>(blk, nx, ny, BS, c0, r0, cw, rh);
+  const float4* __restrict__ rec = records + (size_t)blk * M;
+  if constexpr (PLACE == kAblLds) {
+    for (int m = threadIdx.x; m < M; m += BS) lrec[m] = rec[m];
+    __syncthreads();
+  }
+  const int c = c0 + (MAP == kAblLinear ? (int)threadIdx.x : (int)threadIdx.x % cw);
+  const int r = r0 + (MAP == kAblLinear ? 0 : (int)threadIdx.x / cw);
+  const int cc = centre_col(c0, min(nx - c0, cw)), rc = r0 + (max(min(ny - r0, rh), 1) - 1) / 2;
+  const float u = (float)(2 * (c - cc)), v = (float)(2 * (r - rc));
+  const float u2 = MAP == kAblLinear ? u * u : u * u + v * v;
+  // a lane-varying zero: makes the GLOBAL placement's record address a per-lane (vector) address
+  int z = 0;
+  if constexpr (PLACE == kAblGlobal) asm volatile("v_mov_b32 %0, 0" : "=v"(z));
+  auto load = [&](int m) {
+    if constexpr (PLACE == kAblLds) return lrec[m];
+    if constexpr (PLACE == kAblScalar) return rec[__builtin_amdgcn_readfirstlane(m)];
+    return rec[m + z];
+  };
+  float sr = 0.0f, si = 0.0f;
+  auto term = [&](const float4& q) {
+    float t;
+    if constexpr (MAP == kAblLinear) {
+      t = __builtin_fmaf(q.y, u2, __builtin_fmaf(q.x, u, q.z));
+    } else {
+      t = __builtin_fmaf(q.z, u2, __builtin_fmaf(q.x, u, __builtin_fmaf(q.y, v, q.w)));
+    }
+    sr += __builtin_amdgcn_cosf(t);
+    si += __builtin_amdgcn_sinf(t);
+  };
+  // eight records in flight per step, alike for every placement
+  int m = 0;
+  for (; m + 8 <= M; m += 8) {
+    float4 q[8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) q[i] = load(m + i);
+#pragma unroll
+    for (int i = 0; i < 8; ++i) term(q[i]);
+  }
+  for (; m < M; ++m) term(load(m));
+  if (c < nx && r < ny) phase[(size_t)r * nx + c] = phase_of(si, sr);
+}
+
 // ------------------------------------------------------------------ helpers
 
 // 8-bit SLM frame: grey level = rint(phase * 256 / (2 pi)) mod 256 (FP32 product, round to even).
@@ -1580,6 +1688,50 @@ hipError_t launch_sep(hipStream_t s, const SepArgs& a) {
     case 1: return sep_mode<1>(s, a);
     case 2: return sep_mode<2>(s, a);
     default: return sep_mode<4>(s, a);
+  }
+}
+
+int abl_blocks(int mapping, int bs, int nx, int ny) {
+  if (mapping == kAblLinear) return ((nx + bs - 1) / bs) * ny;
+  const int side = bs == 64 ? 8 : 16;
+  return ((nx + side - 1) / side) * ((ny + side - 1) / side);
+}
+
+hipError_t launch_abl_records(hipStream_t s, int mapping, int bs, int nx, int ny, int M, const TrapCoef* coef,
+                              const TrapState* st, float4* records) {
+  const int nb = abl_blocks(mapping, bs, nx, ny);
+  if (mapping == kAblLinear)
+    hipLaunchKernelGGL(k_abl_records<kAblLinear>, dim3(nb), dim3(256), 0, s, coef, st, M, nx, ny, bs, records);
+  else
+    hipLaunchKernelGGL(k_abl_records<kAblSquare>, dim3(nb), dim3(256), 0, s, coef, st, M, nx, ny, bs, records);
+  return hipGetLastError();
+}
+
+template <int PLACE, int MAP>
+hipError_t abl_bs(hipStream_t s, int bs, int nx, int ny, int M, const float4* records, float* phase) {
+  const int nb = abl_blocks(MAP, bs, nx, ny);
+  if (bs == 64)
+    hipLaunchKernelGGL((k_abl_pixel<PLACE, MAP, 64>), dim3(nb), dim3(64), 0, s, records, M, nx, ny, phase);
+  else
+    hipLaunchKernelGGL((k_abl_pixel<PLACE, MAP, 256>), dim3(nb), dim3(256), 0, s, records, M, nx, ny, phase);
+  return hipGetLastError();
+}
+
+template <int PLACE>
+hipError_t abl_map(hipStream_t s, int mapping, int bs, int nx, int ny, int M, const float4* records, float* phase) {
+  return mapping == kAblLinear ? abl_bs<PLACE, kAblLinear>(s, bs, nx, ny, M, records, phase)
+                               : abl_bs<PLACE, kAblSquare>(s, bs, nx, ny, M, records, phase);
+}
+
+hipError_t launch_abl_pixel(hipStream_t s, int placement, int mapping, int bs, int nx, int ny, int M,
+                            const float4* records, float* phase) {
+  if ((bs != 64 && bs != 256) || (mapping != kAblLinear && mapping != kAblSquare) || M < 1 || M > kMaxTraps)
+    return hipErrorInvalidValue;
+  switch (placement) {
+    case kAblLds: return abl_map<kAblLds>(s, mapping, bs, nx, ny, M, records, phase);
+    case kAblScalar: return abl_map<kAblScalar>(s, mapping, bs, nx, ny, M, records, phase);
+    case kAblGlobal: return abl_map<kAblGlobal>(s, mapping, bs, nx, ny, M, records, phase);
+    default: return hipErrorInvalidValue;
   }
 }
 

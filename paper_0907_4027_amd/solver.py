@@ -237,6 +237,23 @@ class Context:
                                                    _vp(phase), _vp(V), ms))
         return np.array(ms[:], dtype=np.float64)
 
+    def hot_pixel_pass_variant(self, slm, xyz, theta0, placement: str = "lds", mapping: str = "linear",
+                               block: int = 256, reps: int = 20, phase=None):
+        """Random-superposition pixel pass with the trap records in LDS / read by scalar loads / read by
+        per-lane global loads, pixels in row segments or square tiles (the ablation of the paper's
+        Table 1).  Returns (phase [ny, nx], mean ms per launch)."""
+        s = as_slm(slm)
+        x = _host_f64(xyz, cols=3)
+        M = x.shape[0]
+        th = _host_f64(theta0, rows=M)
+        pl = {"lds": _lib.HOT_REC_LDS, "scalar": _lib.HOT_REC_SCALAR, "global": _lib.HOT_REC_GLOBAL}[placement]
+        mp = {"linear": _lib.HOT_MAP_LINEAR, "square": _lib.HOT_MAP_SQUARE}[mapping]
+        phase = self._dev(phase, s.nx * s.ny, "phase") if phase is not None else self._new(s.ny, s.nx)
+        ms = (C.c_float * 1)()
+        check(self._lib, self._lib.hot_pixel_pass_variant(self._ctx, C.byref(s), M, _dp(x), _dp(th), int(pl), int(mp),
+                                                          int(block), int(reps), _vp(phase), ms))
+        return phase, float(ms[0])
+
     def hot_probe_issue(self, kind: int, waves_per_simd: int, reps: int) -> dict:
         """Issue-rate micro-benchmark (kind 0 FMA, 1 sin/cos, 2 the direct passes' term); see
         include/hot.h.  Returns rates per second, the waves' mean shader clock and timings."""

@@ -288,6 +288,30 @@ def test_stored_trap_groups(hot, nx, ny, m):
     o = oracle_solve("gsw", p, p.iters)
     assert_phase(to_np(g.phase), o["phi"])
     assert_V(to_np(g.V), o["V"])
+
+
+def test_batched_autotuner_keeps_parity(hot, tmp_path):
+    """The batched launch's autotuner (traps per lane, rows, pixels per lane over short batched solves)
+    caches its choice, and the batch solved with it matches the oracle."""
+    from paper_0907_4027_amd import autotune
+    bt = W.c4(5)
+    bt.iters = 4
+    cache = str(tmp_path / "tuning.json")
+    with hot.Context(0) as c:
+        small = {"traps_per_lane": (0, 3, 5), "rows": (1, 2), "pixels_per_lane": (0,)}
+        rows = autotune.sweep_batched(c, bt.slm, bt.counts, bt.xyz, bt.theta0, iters=1, reps=2, candidates=small)
+        assert len(rows) == 6 and rows[0]["ms_per_solve"] <= rows[-1]["ms_per_solve"]
+        r1 = autotune.tune_batched(c, bt.slm, bt.counts, bt.xyz, bt.theta0, cache=cache, iters=1, reps=2)
+        r2 = autotune.tune_batched(c, bt.slm, bt.counts, bt.xyz, bt.theta0, cache=cache)
+        assert r1["table"] is not None and r2["table"] is None and r1["knobs"] == r2["knobs"]
+        r = c.hot_gsw_batched(bt.slm, bt.counts, bt.xyz, bt.theta0, bt.iters)
+        torch.cuda.synchronize()
+    ph, V, o = to_np(r.phase), to_np(r.V), bt.offsets()
+    for b in (0, bt.b - 1):
+        p = bt.problem(b)
+        ref = oracle.solve("gsw", p.slm, p.xyz, p.theta0, bt.iters)
+        assert_phase(ph[b], ref["phi"])
+        assert_V(V[o[b]:o[b + 1]], ref["V"])
     assert_stats(g.stats, o["stats"])
 
 
@@ -497,6 +521,30 @@ def test_tuning_rejects_unsupported_shapes(hot):
     assert_V(to_np(g.V), o["V"])
 
 
+def test_batched_autotuner_keeps_parity(hot, tmp_path):
+    """The batched launch's autotuner (traps per lane, rows, pixels per lane over short batched solves)
+    caches its choice, and the batch solved with it matches the oracle."""
+    from paper_0907_4027_amd import autotune
+    bt = W.c4(5)
+    bt.iters = 4
+    cache = str(tmp_path / "tuning.json")
+    with hot.Context(0) as c:
+        small = {"traps_per_lane": (0, 3, 5), "rows": (1, 2), "pixels_per_lane": (0,)}
+        rows = autotune.sweep_batched(c, bt.slm, bt.counts, bt.xyz, bt.theta0, iters=1, reps=2, candidates=small)
+        assert len(rows) == 6 and rows[0]["ms_per_solve"] <= rows[-1]["ms_per_solve"]
+        r1 = autotune.tune_batched(c, bt.slm, bt.counts, bt.xyz, bt.theta0, cache=cache, iters=1, reps=2)
+        r2 = autotune.tune_batched(c, bt.slm, bt.counts, bt.xyz, bt.theta0, cache=cache)
+        assert r1["table"] is not None and r2["table"] is None and r1["knobs"] == r2["knobs"]
+        r = c.hot_gsw_batched(bt.slm, bt.counts, bt.xyz, bt.theta0, bt.iters)
+        torch.cuda.synchronize()
+    ph, V, o = to_np(r.phase), to_np(r.V), bt.offsets()
+    for b in (0, bt.b - 1):
+        p = bt.problem(b)
+        ref = oracle.solve("gsw", p.slm, p.xyz, p.theta0, bt.iters)
+        assert_phase(ph[b], ref["phi"])
+        assert_V(V[o[b]:o[b + 1]], ref["V"])
+
+
 @pytest.mark.parametrize("variant", ["onthefly", "separable", "stored"])
 def test_graph_replays_match_eager(hot, variant):
     """The cached hipGraph of a solve, replayed several times with other eager work and
@@ -615,6 +663,30 @@ def test_separable_every_block_width(hot, waves, chunk, split):
     o = oracle_solve("gsw", p, p.iters)
     assert_phase(to_np(g.phase), o["phi"])
     assert_V(to_np(g.V), o["V"])
+
+
+def test_batched_autotuner_keeps_parity(hot, tmp_path):
+    """The batched launch's autotuner (traps per lane, rows, pixels per lane over short batched solves)
+    caches its choice, and the batch solved with it matches the oracle."""
+    from paper_0907_4027_amd import autotune
+    bt = W.c4(5)
+    bt.iters = 4
+    cache = str(tmp_path / "tuning.json")
+    with hot.Context(0) as c:
+        small = {"traps_per_lane": (0, 3, 5), "rows": (1, 2), "pixels_per_lane": (0,)}
+        rows = autotune.sweep_batched(c, bt.slm, bt.counts, bt.xyz, bt.theta0, iters=1, reps=2, candidates=small)
+        assert len(rows) == 6 and rows[0]["ms_per_solve"] <= rows[-1]["ms_per_solve"]
+        r1 = autotune.tune_batched(c, bt.slm, bt.counts, bt.xyz, bt.theta0, cache=cache, iters=1, reps=2)
+        r2 = autotune.tune_batched(c, bt.slm, bt.counts, bt.xyz, bt.theta0, cache=cache)
+        assert r1["table"] is not None and r2["table"] is None and r1["knobs"] == r2["knobs"]
+        r = c.hot_gsw_batched(bt.slm, bt.counts, bt.xyz, bt.theta0, bt.iters)
+        torch.cuda.synchronize()
+    ph, V, o = to_np(r.phase), to_np(r.V), bt.offsets()
+    for b in (0, bt.b - 1):
+        p = bt.problem(b)
+        ref = oracle.solve("gsw", p.slm, p.xyz, p.theta0, bt.iters)
+        assert_phase(ph[b], ref["phi"])
+        assert_V(V[o[b]:o[b + 1]], ref["V"])
     assert_stats(g.stats, o["stats"])
 
 
@@ -749,6 +821,21 @@ def test_square_grid_sweep_case_matches_oracle(ctx):
     assert g.stats[1, 1] > g.stats[0, 1]
 
 
+@pytest.mark.parametrize("placement", ["lds", "scalar", "global"])
+@pytest.mark.parametrize("mapping", ["linear", "square"])
+@pytest.mark.parametrize("block", [64, 256])
+def test_table1_ablation_variants_match_oracle(ctx, placement, mapping, block):
+    """Every placement x mapping x block size of the ablated pixel pass gives the random-superposition
+    mask of the oracle (a grid ragged in both directions for every tile shape)."""
+    p = W.random_problem(470, 203, 91, 37)
+    phase, ms = ctx.hot_pixel_pass_variant(p.slm, p.xyz, p.theta0, placement=placement, mapping=mapping,
+                                           block=block, reps=2)
+    torch.cuda.synchronize()
+    assert ms > 0
+    ref = oracle.backward(p.slm, p.xyz, None, p.theta0)
+    assert_phase(to_np(phase), ref)
+
+
 def test_autotuner_caches_and_keeps_parity(hot, tmp_path):
     from paper_0907_4027_amd import autotune
     p = W.random_problem(420, 192, 160, 30, 4)
@@ -761,6 +848,32 @@ def test_autotuner_caches_and_keeps_parity(hot, tmp_path):
         r2 = autotune.tune(c, p.slm, p.xyz, p.theta0, cache=cache, reps=3)
         assert r1["table"] is not None and r2["table"] is None and r1["knobs"] == r2["knobs"]
         g = run(c, "gsw", p)
+        t1 = autotune.table1_sweep(c, p.slm, p.xyz, p.theta0, reps=2)
+        assert len(t1) == 12 and t1[0]["ms_per_pass"] <= t1[-1]["ms_per_pass"]
     o = oracle_solve("gsw", p, p.iters)
     assert_phase(to_np(g.phase), o["phi"])
     assert_V(to_np(g.V), o["V"])
+
+
+def test_batched_autotuner_keeps_parity(hot, tmp_path):
+    """The batched launch's autotuner (traps per lane, rows, pixels per lane over short batched solves)
+    caches its choice, and the batch solved with it matches the oracle."""
+    from paper_0907_4027_amd import autotune
+    bt = W.c4(5)
+    bt.iters = 4
+    cache = str(tmp_path / "tuning.json")
+    with hot.Context(0) as c:
+        small = {"traps_per_lane": (0, 3, 5), "rows": (1, 2), "pixels_per_lane": (0,)}
+        rows = autotune.sweep_batched(c, bt.slm, bt.counts, bt.xyz, bt.theta0, iters=1, reps=2, candidates=small)
+        assert len(rows) == 6 and rows[0]["ms_per_solve"] <= rows[-1]["ms_per_solve"]
+        r1 = autotune.tune_batched(c, bt.slm, bt.counts, bt.xyz, bt.theta0, cache=cache, iters=1, reps=2)
+        r2 = autotune.tune_batched(c, bt.slm, bt.counts, bt.xyz, bt.theta0, cache=cache)
+        assert r1["table"] is not None and r2["table"] is None and r1["knobs"] == r2["knobs"]
+        r = c.hot_gsw_batched(bt.slm, bt.counts, bt.xyz, bt.theta0, bt.iters)
+        torch.cuda.synchronize()
+    ph, V, o = to_np(r.phase), to_np(r.V), bt.offsets()
+    for b in (0, bt.b - 1):
+        p = bt.problem(b)
+        ref = oracle.solve("gsw", p.slm, p.xyz, p.theta0, bt.iters)
+        assert_phase(ph[b], ref["phi"])
+        assert_V(V[o[b]:o[b + 1]], ref["V"])
