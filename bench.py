@@ -271,14 +271,23 @@ def main():
 
     # ---------------------------------------------------------------- hardware-counter runs
     if args.only == "counters":
-        # a plain device-to-device copy of known size (FETCH_SIZE / WRITE_SIZE calibration), then the
-        # pass-timing launches of the headline kernel
+        # a plain device-to-device copy of known size (FETCH_SIZE / WRITE_SIZE calibration), then a few
+        # launches of every kernel family: the headline iteration kernel (in the per-pass timing below),
+        # the stored variant's passes at 512^2 x 100 and 1024^2 x 256, and the separable iteration
         src = torch.ones(64 << 20, device="cuda")
         dst = torch.empty_like(src)
         for _ in range(3):
             dst.copy_(src)
         sync()
-        log(f"[bench] counters: 3 copies of {src.numel() * 4 >> 20} MiB")
+        del src, dst
+        log("[bench] counters: 3 copies of 256 MiB")
+        for variant, probs, reps in (("stored", (W.c2(), W.c3()), 3), ("separable", (W.c2(), W.c3()), 5)):
+            with hot.Context(0) as cc:
+                cc.set_variant(variant)
+                for q in probs:
+                    pm = cc.hot_time_passes(q.slm, q.xyz, q.theta0, reps=reps)
+                    log(f"[bench] counters: {variant} {q.name} passes {pm[0]:.4f} {pm[2]:.4f} {pm[3]:.4f} ms")
+        sync()
 
     # ---------------------------------------------------------------- per-pass timings -> roofline
     roof = None

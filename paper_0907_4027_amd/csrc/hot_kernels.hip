@@ -1149,15 +1149,15 @@ k_sep(const TrapCoef* __restrict__ coef, const HoloDesc* __restrict__ hd, const 
   // the update's inputs arrive, and only then does the GS/GSW update.
   const VAcc vacc{acc_in, T, off, unscale};
   const bool lead = blockIdx.x == 0 && blockIdx.y == 0;
-  TrapCoef c_first = {0.0, 0.0, 0.0, 0.0f, 0.0f};
+  // unconditional loads (threads past M read trap M - 1; their copies are never used as trap
+  // threadIdx.x), so the values stay in registers
+  const int tm = min((int)threadIdx.x, M - 1);
+  const TrapCoef c_first = coef[off + tm];
   float2 v_first = make_float2(0.0f, 0.0f);
   TrapState s_first = {0.0f, 0.0f, 0.0f, 0.0f};
-  if ((int)threadIdx.x < M) {
-    c_first = coef[off + threadIdx.x];
-    if (kPixel && MODE != 3) {
-      s_first = st_in[off + threadIdx.x];
-      if (MODE == 0 && upd != 0) v_first = vacc(threadIdx.x);
-    }
+  if (kPixel && MODE != 3) {
+    s_first = st_in[off + tm];
+    if (MODE == 0 && upd != 0) v_first = vacc(tm);
   }
   if (MODE == 0 && lead) {
     for (int i = threadIdx.x; i < kAccRegions * M; i += NT) {
@@ -1166,7 +1166,7 @@ k_sep(const TrapCoef* __restrict__ coef, const HoloDesc* __restrict__ hd, const 
     }
   }
   for (int m = NT + (int)threadIdx.x; m < Mp; m += NT) cf[m] = m < M ? coef[off + m] : TrapCoef{0.0, 0.0, 0.0, 0.0f, 0.0f};
-  if ((int)threadIdx.x < Mp) cf[threadIdx.x] = c_first;
+  if ((int)threadIdx.x < Mp) cf[threadIdx.x] = (int)threadIdx.x < M ? c_first : TrapCoef{0.0, 0.0, 0.0, 0.0f, 0.0f};
   __syncthreads();
   if constexpr (kPixel) {
     tables_x(0, min(sc, Mp));
