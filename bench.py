@@ -97,7 +97,11 @@ def measure_peaks(ctx, log):
     import torch
     # shader cycles per lane operation in the model: a wave64 FMA takes 4, a sin or cos 8, a term
     # (4 FMA + sin + cos) 32
-    kinds = {0: ("fma", 4.0 / 64), 1: ("sincos", 8.0 / 64), 2: ("term", 32.0 / 64)}
+    # The matrix kinds count FLOPs, against the published FP32 matrix peak (157.3 TFLOP/s at
+    # 2.4 GHz: 64 FLOPs per SIMD per cycle, a 16x16x4 product every 32 cycles)
+    kinds = {0: ("fma", 4.0 / 64), 1: ("sincos", 8.0 / 64), 2: ("term", 32.0 / 64),
+             3: ("mfma_16x16x4_f32", 1.0 / 64), 4: ("mfma_16x16x4_f32_one_accumulator", 1.0 / 64),
+             5: ("mfma_32x32x2_f32", 1.0 / 64)}
     res = {}
     simds = 256 * 4
     for kind, (name, cyc_per_op) in kinds.items():
@@ -112,6 +116,10 @@ def measure_peaks(ctx, log):
                               "vs_model_at_2.4GHz": round(r["ops_per_s"] / model_24, 4),
                               "span_ms": round(r["span_s"] * 1e3, 3), "event_ms": round(r["event_s"] * 1e3, 3)}
         res[name] = rows
+        if kind >= 3:
+            for v in rows.values():
+                v["cycles_per_product_per_SIMD"] = round((2048 if kind < 5 else 4096) * SIMDS * v["clock_GHz"] * 1e9
+                                                         / v["ops_per_s"], 2)
         log(f"[bench] probe {name}: " + "  ".join(
             f"{w}w {v['ops_per_s'] / 1e12:.2f}T/s @{v['clock_GHz']:.2f}GHz ({v['vs_model_at_measured_clock']:.3f})"
             for w, v in rows.items()))

@@ -256,8 +256,12 @@ int hot_pixel_pass_variant(hot_ctx* ctx, const hot_slm* slm, int32_t M, const do
  *   kind 1  hardware sin/cos (128 per repetition, 8 independent chains)
  *   kind 2  the term of the direct passes (16 per repetition): two FMAs form the phase
  *           (Eq. 2 in revolutions), sin and cos, two FMAs accumulate (plus one add per repetition)
+ *   kind 3  FP32 matrix products 16x16x4, four independent accumulators per wave
+ *   kind 4  FP32 matrix products 16x16x4, one accumulator (each product waits for the last)
+ *   kind 5  FP32 matrix products 32x32x2, four independent accumulators per wave
  * after a short warm-up launch.  Writes, to host `out` (6 doubles):
- *   out[0] operations per second: lane-level FMAs (kind 0), sin/cos (kind 1) or terms (kind 2),
+ *   out[0] operations per second: lane-level FMAs (kind 0), sin/cos (kind 1), terms (kind 2) or
+ *          FLOPs (kinds 3-5),
  *          over the span from the first wave's start to the last wave's end (s_memrealtime,
  *          100 MHz); out[1] mean shader clock of the waves [Hz] (s_memtime cycles over the same
  *          waves' real time); out[2] that span [s]; out[3] the launch's duration by HIP events [s];

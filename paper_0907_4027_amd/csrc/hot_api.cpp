@@ -346,6 +346,10 @@ int prepare_into(hot_ctx* c, const hot_slm* slm, int B, const int32_t* counts, c
       const size_t budget = (size_t)kSepLdsMax / bpc;
       if (budget <= fixed + row_bytes) continue;
       sc = (int)std::min<size_t>(mp / 16, (budget - fixed) / row_bytes) * 16;
+      // equal super-chunks (multiples of 16): no short last one, whose tables (the ones the
+      // trap pass reuses) would leave most lanes idle
+      const int nsc = (mp + sc - 1) / sc;
+      sc = ((mp + nsc - 1) / nsc + 15) / 16 * 16;
       break;
     }
     if (c->tune_sepc > 0) sc = std::min(mp, c->tune_sepc);
@@ -1248,7 +1252,7 @@ int hot_pixel_pass_variant(hot_ctx* c, const hot_slm* slm, int32_t M, const doub
 
 int hot_probe_issue(hot_ctx* c, int kind, int waves_per_simd, int64_t reps, double* out) {
   if (!c) return fail(HOT_EINVAL, "ctx is NULL");
-  if (kind < 0 || kind > 2) return fail(HOT_EINVAL, "probe kind %d outside 0..2", kind);
+  if (kind < 0 || kind > 5) return fail(HOT_EINVAL, "probe kind %d outside 0..5", kind);
   if (waves_per_simd != 1 && waves_per_simd != 2 && waves_per_simd != 4 && waves_per_simd != 8)
     return fail(HOT_EINVAL, "waves per SIMD must be 1, 2, 4 or 8");
   if (reps < 1 || reps > (1LL << 24)) return fail(HOT_EINVAL, "reps = %lld outside 1..2^24", (long long)reps);

@@ -1286,12 +1286,15 @@ k_sep(const TrapCoef* __restrict__ coef, const HoloDesc* __restrict__ hd, const 
   if constexpr (kTrap) {
     // per tile of 16 traps: T^T[r][m] = sum_c E[r][c] conj X[m][c], then sum_r conj Y[m][r] T^T[r][m]
     const int nblk = gridDim.x * gridDim.y, blk = blockIdx.y * gridDim.x + blockIdx.x;
+    // super-chunks in reverse order: the pixel pass's last one is still in LDS (tables X and Y),
+    // so it is taken first and only the others are rebuilt.  Each trap's sum lies within one
+    // super-chunk, so the order changes no result.
     const float2* xcol = xt + (tw * 16 + 4 * g) * XS + li;
     const float2* ycol = yt + (4 * g) * XS + li;
-    for (int s = 0; s < nsc; ++s) {
+    for (int s = nsc - 1; s >= 0; --s) {
       const int k0 = s * sc, n = min(sc, Mp - k0);
-      if (!kPixel || nsc > 1) {  // one pixel-pass super-chunk is still in LDS
-        if (kPixel || s > 0) __syncthreads();
+      if (!kPixel || s < nsc - 1) {
+        if (kPixel || s < nsc - 1) __syncthreads();  // the previous super-chunk is no longer read
         tables_x(k0, n);
         tables_y(k0, n, false);
         __syncthreads();

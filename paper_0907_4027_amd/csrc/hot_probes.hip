@@ -9,6 +9,10 @@
 //   * the V_SIN_F32 / V_COS_F32 issue rate;
 //   * whether the two overlap: a stream with the term's exact mix (4 FMA : 1 sin : 1 cos) runs
 //     at the sum of the two costs (no overlap) or faster;
+// The separable variant runs both passes as FP32 matrix products (V_MFMA_F32_16X16X4_F32), so
+// the matrix pipe's issue rate is measured too: with four independent accumulators per wave,
+// with one accumulator (each product waits for the previous one's result), and for the 32x32x2
+// shape;
 // each at 1, 2, 4 and 8 waves per SIMD, together with the shader clock the waves ran at
 // (s_memtime counts shader cycles, s_memrealtime a constant 100 MHz clock).  Every wave writes
 // its own clock stamps (vector stores) and one value derived from all its results, so no work
@@ -29,6 +33,13 @@ __device__ __forceinline__ unsigned long long real_clock() { return __builtin_am
 // KIND 2: the term of a direct pass, 16 per repetition: t = fma(g, U^2, fma(a, U, c));
 //         re += w cos t; im += w sin t (64 FMAs + 32 transcendentals per repetition, plus one
 //         add that moves c on).
+// KIND 3: V_MFMA_F32_16X16X4_F32, 4 independent accumulators (16 products per repetition).
+// KIND 4: V_MFMA_F32_16X16X4_F32, one accumulator: every product depends on the one before (16 per
+//         repetition).
+// KIND 5: V_MFMA_F32_32X32X2_F32, 4 independent accumulators (16 products per repetition).
+typedef float probe_f32x4 __attribute__((ext_vector_type(4)));
+typedef float probe_f32x16 __attribute__((ext_vector_type(16)));
+
 template <int KIND>
 __global__ void __launch_bounds__(1024)
 k_probe(long long reps, float seed, float* __restrict__ sink, unsigned long long* __restrict__ stamps) {
@@ -67,6 +78,41 @@ k_probe(long long reps, float seed, float* __restrict__ sink, unsigned long long
     }
 #pragma unroll
     for (int i = 0; i < 8; ++i) out += s[i];
+  } else if constexpr (KIND == 3 || KIND == 4) {
+    constexpr int NC = KIND == 3 ? 4 : 1;
+    probe_f32x4 acc[NC];
+#pragma unroll
+    for (int i = 0; i < NC; ++i) acc[i] = probe_f32x4{seed, 0.0f, 0.0f, 0.0f};
+    const float a = 1.0e-3f * seed * (float)(lane + 1), bv = 1.0e-3f * seed;
+    for (long long r = 0; r < reps; ++r) {
+#pragma unroll
+      for (int u = 0; u < kProbeUnroll / NC; ++u) {
+#pragma unroll
+        for (int i = 0; i < NC; ++i) acc[i] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, bv, acc[i], 0, 0, 0);
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < NC; ++i) out += (acc[i][0] + acc[i][1]) + (acc[i][2] + acc[i][3]);
+  } else if constexpr (KIND == 5) {
+    probe_f32x16 acc[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+#pragma unroll
+      for (int e = 0; e < 16; ++e) acc[i][e] = e == 0 ? seed : 0.0f;
+    }
+    const float a = 1.0e-3f * seed * (float)(lane + 1), bv = 1.0e-3f * seed;
+    for (long long r = 0; r < reps; ++r) {
+#pragma unroll
+      for (int u = 0; u < kProbeUnroll / 4; ++u) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) acc[i] = __builtin_amdgcn_mfma_f32_32x32x2f32(a, bv, acc[i], 0, 0, 0);
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+#pragma unroll
+      for (int e = 0; e < 16; ++e) out += acc[i][e];
+    }
   } else {
     // a lane's pixel coordinate and sixteen trap records (a, g, w), as in the pixel pass; c (the
     // row constant) changes once per repetition, so every term is computed anew
@@ -131,6 +177,9 @@ int probe_ops_per_rep(int kind) {
     case 0: return 8 * kProbeUnroll;         // FMA
     case 1: return 8 * kProbeUnroll;         // sin / cos
     case 2: return kProbeUnroll;             // terms (4 FMA + sin + cos each; plus 1 add per repetition)
+    case 3:                                  // FLOPs per lane: 2 x 16 x 16 x 4 per product over 64 lanes
+    case 4: return kProbeUnroll * 32;
+    case 5: return kProbeUnroll * 64;        // 2 x 32 x 32 x 2 per product over 64 lanes
     default: return 0;
   }
 }
@@ -141,6 +190,9 @@ hipError_t launch_probe(hipStream_t s, int kind, int blocks, int threads, long l
     case 0: hipLaunchKernelGGL(k_probe<0>, dim3(blocks), dim3(threads), 0, s, reps, seed, sink, stamps); break;
     case 1: hipLaunchKernelGGL(k_probe<1>, dim3(blocks), dim3(threads), 0, s, reps, seed, sink, stamps); break;
     case 2: hipLaunchKernelGGL(k_probe<2>, dim3(blocks), dim3(threads), 0, s, reps, seed, sink, stamps); break;
+    case 3: hipLaunchKernelGGL(k_probe<3>, dim3(blocks), dim3(threads), 0, s, reps, seed, sink, stamps); break;
+    case 4: hipLaunchKernelGGL(k_probe<4>, dim3(blocks), dim3(threads), 0, s, reps, seed, sink, stamps); break;
+    case 5: hipLaunchKernelGGL(k_probe<5>, dim3(blocks), dim3(threads), 0, s, reps, seed, sink, stamps); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
