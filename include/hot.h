@@ -193,7 +193,9 @@ int hot_gsw_noalloc(hot_ctx* ctx, const hot_slm* slm, int32_t M, const double* x
  *   xyz     host, T x 3;  theta0 host, T [rad] (required)
  *   phase   device, B x N floats;  V device, 2T floats
  *   stats   host, B x (iters+1) entries (hologram-major) or NULL
- * Each hologram's result equals hot_gsw on that hologram alone (same kernels per pixel tile). */
+ * Each hologram's result matches hot_gsw on that hologram alone within the parity tolerance, and
+ * bit for bit when both runs use the same launch shape (hot_set_tuning): the launch shape is
+ * otherwise chosen per launch, and with it the order of each block's floating-point trap sums. */
 int hot_gsw_batched(hot_ctx* ctx, const hot_slm* slm, int32_t B, const int32_t* M, const double* xyz,
                     const double* theta0, int32_t iters, float* phase, float* V, hot_stats* stats);
 

@@ -73,6 +73,14 @@ __device__ __forceinline__ float wave_min(float v) {
   return fminf(fminf(rows_of(v, 0), rows_of(v, 16)), fminf(rows_of(v, 32), rows_of(v, 48)));
 }
 
+// A caller's phase [rad] in revolutions, reduced to [0, 1] (1 is the same angle as 0): product and
+// reduction in FP64, so a mask far outside [0, 2 pi) (an optimiser's drifting phase, say) loses
+// nothing beyond its own FP32 rounding and stays inside the hardware sin/cos domain.  Once per pixel.
+__device__ __forceinline__ float caller_phase_rev(float ph) {
+  const double t = (double)ph * 0.15915494309189533577;  // 1 / (2 pi)
+  return (float)(t - __builtin_floor(t));
+}
+
 __device__ __forceinline__ float wrap_phase(float ph) { return ph < 0.0f ? ph + kTwoPi : ph; }
 
 // arg(x + i y) in [0, 2pi] (arg 0 = 0).  The octant is folded onto t = min(|x|,|y|) / max(|x|,|y|)
@@ -724,8 +732,8 @@ k_forward(const TrapCoef* __restrict__ coef, const HoloDesc* __restrict__ hd, co
     if (l < kSpan && c < len) {
       const int cc = centre_col(cbeg + kSpan * h, min(len - kSpan * h, kSpan));
       const float u = (float)(2 * (cbeg + c - cc));
-      // any phase the caller passes, wrapped to one period (exact)
-      px[i] = make_float4(__builtin_amdgcn_fractf(ph[c] * kInv2Pi), u, u * u, 1.0f);
+      // any phase the caller passes, in revolutions within one period
+      px[i] = make_float4(caller_phase_rev(ph[c]), u, u * u, 1.0f);
     } else {
       px[i] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
     }
@@ -1253,7 +1261,7 @@ k_sep(const TrapCoef* __restrict__ coef, const HoloDesc* __restrict__ hd, const 
     for (int v = 0; v < 4; ++v) {
       if constexpr (MODE == 3) {
         if (in[v]) {
-          const float pr = __builtin_amdgcn_fractf(phase[pix0 + v] * kInv2Pi);
+          const float pr = caller_phase_rev(phase[pix0 + v]);
           grad[pix0 + v] =
               inv_n * (__builtin_amdgcn_cosf(pr) * sim[v] - __builtin_amdgcn_sinf(pr) * sre[v]);  // Im(e^{-i phi} S)
         }
@@ -1277,7 +1285,7 @@ k_sep(const TrapCoef* __restrict__ coef, const HoloDesc* __restrict__ hd, const 
   } else {
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
-      const float pr = in[v] ? __builtin_amdgcn_fractf(phase[pix0 + v] * kInv2Pi) : 0.0f;
+      const float pr = in[v] ? caller_phase_rev(phase[pix0 + v]) : 0.0f;
       er[v] = in[v] ? __builtin_amdgcn_cosf(pr) : 0.0f;
       ei[v] = in[v] ? __builtin_amdgcn_sinf(pr) : 0.0f;
     }

@@ -135,6 +135,29 @@ def test_trap_field_gradient_8x512sq_64(hot, vctx):
     assert abs(L.item() - Ltot) <= 1e-4 * abs(Ltot)
 
 
+@pytest.mark.parametrize("turns", [300, 3000])
+def test_unwrapped_caller_phase(vctx, turns):
+    """A caller's mask need not lie in [0, 2 pi): a GS mask plus 2 pi k per pixel, |k| up to `turns`
+    (far past the 256 revolutions of the hardware sin/cos), gives Eq. 1 and its adjoint of the same
+    FP32 values within the usual bars."""
+    p = W.random_problem(540, 300, 77, 64)
+    phi0 = to_np(vctx.hot_gs(p.slm, p.xyz, p.theta0, 5).phase).ravel()
+    rng = np.random.default_rng(541)
+    k = rng.integers(-turns, turns + 1, p.slm.n)
+    phi = (phi0 + 2 * math.pi * k).astype(np.float32).astype(np.float64)
+    assert np.abs(phi).max() > 2 * math.pi * 0.9 * turns
+    G = (rng.normal(size=p.m) + 1j * rng.normal(size=p.m)).astype(np.complex64).astype(np.complex128)
+    Gt = torch.tensor(np.stack([G.real, G.imag], -1), dtype=torch.float32, device="cuda")
+    ph = to_dev(phi[None], p.slm)
+    V = to_np(vctx.hot_forward_V(p.slm, [p.m], p.xyz, ph))
+    g = to_np(vctx.hot_adjoint(p.slm, [p.m], p.xyz, ph, Gt)).ravel()
+    torch.cuda.synchronize()
+    assert_V(V, oracle.forward(p.slm, p.xyz, phi))
+    ref = oracle.adjoint(p.slm, p.xyz, phi, G)
+    rel = np.linalg.norm(g - ref) / np.linalg.norm(ref)
+    assert rel <= 1e-4, rel
+
+
 @pytest.mark.parametrize("counts", [(3, 64, 131, 17), (1, 200)])
 def test_batched_adjoint_uneven_counts(vctx, counts):
     """Uneven trap counts on a grid ragged in both directions: every hologram's Eq. 1 and gradient."""

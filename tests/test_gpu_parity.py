@@ -231,6 +231,25 @@ def test_batched_equals_plain_and_oracle(ctx):
             assert_V(V[o[b]:o[b + 1]], ref["V"])
 
 
+def test_batched_bitwise_equals_plain_with_same_launch_shape(hot):
+    """With the launch shape fixed by hot_set_tuning, each hologram of a batch is the plain solve of
+    that hologram bit for bit: the per-pixel work is the same, and the trap sums of the blocks meet
+    as integer (fixed-point) additions, exact in any order."""
+    bt = W.c4(4)
+    bt.iters = 6
+    with hot.Context(0) as c:
+        c.set_tuning(pixels_per_lane=2, traps_per_lane=5, segment=512, rows=1, fract=1)
+        r = c.hot_gsw_batched(bt.slm, bt.counts, bt.xyz, bt.theta0, bt.iters)
+        torch.cuda.synchronize()
+        ph, V, st = r.phase.cpu().numpy(), r.V.cpu().numpy(), r.stats
+        o = bt.offsets()
+        for b in range(bt.b):
+            g = run(c, "gsw", bt.problem(b), bt.iters)
+            assert np.array_equal(ph[b], g.phase.cpu().numpy()), f"hologram {b}: phase differs"
+            assert np.array_equal(V[o[b]:o[b + 1]], g.V.cpu().numpy()), f"hologram {b}: V differs"
+            assert np.array_equal(np.asarray(st[b]), np.asarray(g.stats)), f"hologram {b}: statistics differ"
+
+
 @pytest.mark.parametrize("algo,nx,ny,m", [("gsw", 200, 91, 37), ("gs", 256, 64, 100), ("rs", 130, 33, 9)])
 def test_two_rows_per_block(hot, algo, nx, ny, m):
     """Blocks of two rows (one shared update, one set of trap-sum additions per block) give the
