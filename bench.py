@@ -598,7 +598,7 @@ def main():
             f"iterations on 1 thread ({model})")
 
     if ms is None:
-        print(json.dumps({"section": args.only, **out, "roofline": roof}))
+        print(json.dumps({"section": args.only, **out, "roofline": roof, "tuning": tuning}))
         return
     value = N * M * K / (ms * 1e-3)
     line = {

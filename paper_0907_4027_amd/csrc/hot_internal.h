@@ -92,7 +92,8 @@ struct FwdGeom {
 // One fused iteration: (optional GS/GSW update) -> pixel pass -> trap pass, its sums added to acc_out.
 // Direct path: each iteration launch adds its per-block trap sums, as 64-bit fixed point, into
 // kAccRegions regions (one per XCD of an MI355X; waves of XCD x use region x & 7), laid out
-// [region][trap][re, im]; three such buffers rotate over the iterations.
+// [region][trap], one 64-bit word per trap (re and im packed, pack_sum in hot_kernels.hip); three
+// such buffers rotate over the iterations.
 constexpr int kAccRegions = 8;
 
 struct IterArgs {

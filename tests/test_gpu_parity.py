@@ -309,31 +309,6 @@ def test_stored_trap_groups(hot, nx, ny, m):
     assert_V(to_np(g.V), o["V"])
 
 
-def test_batched_autotuner_keeps_parity(hot, tmp_path):
-    """The batched launch's autotuner (traps per lane, rows, pixels per lane over short batched solves)
-    caches its choice, and the batch solved with it matches the oracle."""
-    from paper_0907_4027_amd import autotune
-    bt = W.c4(5)
-    bt.iters = 4
-    cache = str(tmp_path / "tuning.json")
-    with hot.Context(0) as c:
-        small = {"traps_per_lane": (0, 3, 5), "rows": (1, 2), "pixels_per_lane": (0,)}
-        rows = autotune.sweep_batched(c, bt.slm, bt.counts, bt.xyz, bt.theta0, iters=1, reps=2, candidates=small)
-        assert len(rows) == 6 and rows[0]["ms_per_solve"] <= rows[-1]["ms_per_solve"]
-        r1 = autotune.tune_batched(c, bt.slm, bt.counts, bt.xyz, bt.theta0, cache=cache, iters=1, reps=2)
-        r2 = autotune.tune_batched(c, bt.slm, bt.counts, bt.xyz, bt.theta0, cache=cache)
-        assert r1["table"] is not None and r2["table"] is None and r1["knobs"] == r2["knobs"]
-        r = c.hot_gsw_batched(bt.slm, bt.counts, bt.xyz, bt.theta0, bt.iters)
-        torch.cuda.synchronize()
-    ph, V, o = to_np(r.phase), to_np(r.V), bt.offsets()
-    for b in (0, bt.b - 1):
-        p = bt.problem(b)
-        ref = oracle.solve("gsw", p.slm, p.xyz, p.theta0, bt.iters)
-        assert_phase(ph[b], ref["phi"])
-        assert_V(V[o[b]:o[b + 1]], ref["V"])
-    assert_stats(g.stats, o["stats"])
-
-
 # ------------------------------------------------------------------ invariants, determinism, edges
 
 def test_single_trap_closed_form(ctx):
@@ -540,30 +515,6 @@ def test_tuning_rejects_unsupported_shapes(hot):
     assert_V(to_np(g.V), o["V"])
 
 
-def test_batched_autotuner_keeps_parity(hot, tmp_path):
-    """The batched launch's autotuner (traps per lane, rows, pixels per lane over short batched solves)
-    caches its choice, and the batch solved with it matches the oracle."""
-    from paper_0907_4027_amd import autotune
-    bt = W.c4(5)
-    bt.iters = 4
-    cache = str(tmp_path / "tuning.json")
-    with hot.Context(0) as c:
-        small = {"traps_per_lane": (0, 3, 5), "rows": (1, 2), "pixels_per_lane": (0,)}
-        rows = autotune.sweep_batched(c, bt.slm, bt.counts, bt.xyz, bt.theta0, iters=1, reps=2, candidates=small)
-        assert len(rows) == 6 and rows[0]["ms_per_solve"] <= rows[-1]["ms_per_solve"]
-        r1 = autotune.tune_batched(c, bt.slm, bt.counts, bt.xyz, bt.theta0, cache=cache, iters=1, reps=2)
-        r2 = autotune.tune_batched(c, bt.slm, bt.counts, bt.xyz, bt.theta0, cache=cache)
-        assert r1["table"] is not None and r2["table"] is None and r1["knobs"] == r2["knobs"]
-        r = c.hot_gsw_batched(bt.slm, bt.counts, bt.xyz, bt.theta0, bt.iters)
-        torch.cuda.synchronize()
-    ph, V, o = to_np(r.phase), to_np(r.V), bt.offsets()
-    for b in (0, bt.b - 1):
-        p = bt.problem(b)
-        ref = oracle.solve("gsw", p.slm, p.xyz, p.theta0, bt.iters)
-        assert_phase(ph[b], ref["phi"])
-        assert_V(V[o[b]:o[b + 1]], ref["V"])
-
-
 @pytest.mark.parametrize("variant", ["onthefly", "separable", "stored"])
 def test_graph_replays_match_eager(hot, variant):
     """The cached hipGraph of a solve, replayed several times with other eager work and
@@ -682,31 +633,6 @@ def test_separable_every_block_width(hot, waves, chunk, split):
     o = oracle_solve("gsw", p, p.iters)
     assert_phase(to_np(g.phase), o["phi"])
     assert_V(to_np(g.V), o["V"])
-
-
-def test_batched_autotuner_keeps_parity(hot, tmp_path):
-    """The batched launch's autotuner (traps per lane, rows, pixels per lane over short batched solves)
-    caches its choice, and the batch solved with it matches the oracle."""
-    from paper_0907_4027_amd import autotune
-    bt = W.c4(5)
-    bt.iters = 4
-    cache = str(tmp_path / "tuning.json")
-    with hot.Context(0) as c:
-        small = {"traps_per_lane": (0, 3, 5), "rows": (1, 2), "pixels_per_lane": (0,)}
-        rows = autotune.sweep_batched(c, bt.slm, bt.counts, bt.xyz, bt.theta0, iters=1, reps=2, candidates=small)
-        assert len(rows) == 6 and rows[0]["ms_per_solve"] <= rows[-1]["ms_per_solve"]
-        r1 = autotune.tune_batched(c, bt.slm, bt.counts, bt.xyz, bt.theta0, cache=cache, iters=1, reps=2)
-        r2 = autotune.tune_batched(c, bt.slm, bt.counts, bt.xyz, bt.theta0, cache=cache)
-        assert r1["table"] is not None and r2["table"] is None and r1["knobs"] == r2["knobs"]
-        r = c.hot_gsw_batched(bt.slm, bt.counts, bt.xyz, bt.theta0, bt.iters)
-        torch.cuda.synchronize()
-    ph, V, o = to_np(r.phase), to_np(r.V), bt.offsets()
-    for b in (0, bt.b - 1):
-        p = bt.problem(b)
-        ref = oracle.solve("gsw", p.slm, p.xyz, p.theta0, bt.iters)
-        assert_phase(ph[b], ref["phi"])
-        assert_V(V[o[b]:o[b + 1]], ref["V"])
-    assert_stats(g.stats, o["stats"])
 
 
 @pytest.mark.parametrize("algo", ["rs", "gsw"])
