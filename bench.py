@@ -101,7 +101,7 @@ def measure_peaks(ctx, log):
     # 2.4 GHz: 64 FLOPs per SIMD per cycle, a 16x16x4 product every 32 cycles)
     kinds = {0: ("fma", 4.0 / 64), 1: ("sincos", 8.0 / 64), 2: ("term", 32.0 / 64),
              3: ("mfma_16x16x4_f32", 1.0 / 64), 4: ("mfma_16x16x4_f32_one_accumulator", 1.0 / 64),
-             5: ("mfma_32x32x2_f32", 1.0 / 64)}
+             5: ("mfma_32x32x2_f32", 1.0 / 64), 6: ("mfma_16x16x4_f32_with_sincos", 1.0 / 64)}
     res = {}
     simds = 256 * 4
     for kind, (name, cyc_per_op) in kinds.items():
@@ -118,7 +118,7 @@ def measure_peaks(ctx, log):
         res[name] = rows
         if kind >= 3:
             for v in rows.values():
-                v["cycles_per_product_per_SIMD"] = round((2048 if kind < 5 else 4096) * SIMDS * v["clock_GHz"] * 1e9
+                v["cycles_per_product_per_SIMD"] = round((4096 if kind == 5 else 2048) * SIMDS * v["clock_GHz"] * 1e9
                                                          / v["ops_per_s"], 2)
         log(f"[bench] probe {name}: " + "  ".join(
             f"{w}w {v['ops_per_s'] / 1e12:.2f}T/s @{v['clock_GHz']:.2f}GHz ({v['vs_model_at_measured_clock']:.3f})"

@@ -261,9 +261,11 @@ int hot_pixel_pass_variant(hot_ctx* ctx, const hot_slm* slm, int32_t M, const do
  *   kind 3  FP32 matrix products 16x16x4, four independent accumulators per wave
  *   kind 4  FP32 matrix products 16x16x4, one accumulator (each product waits for the last)
  *   kind 5  FP32 matrix products 32x32x2, four independent accumulators per wave
+ *   kind 6  kind 3's products with 64 hardware sin/cos beside them per 16 products (FLOPs of the
+ *           products counted): whether the two pipes overlap
  * after a short warm-up launch.  Writes, to host `out` (6 doubles):
  *   out[0] operations per second: lane-level FMAs (kind 0), sin/cos (kind 1), terms (kind 2) or
- *          FLOPs (kinds 3-5),
+ *          FLOPs (kinds 3-6),
  *          over the span from the first wave's start to the last wave's end (s_memrealtime,
  *          100 MHz); out[1] mean shader clock of the waves [Hz] (s_memtime cycles over the same
  *          waves' real time); out[2] that span [s]; out[3] the launch's duration by HIP events [s];

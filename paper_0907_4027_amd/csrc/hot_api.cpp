@@ -1252,7 +1252,7 @@ int hot_pixel_pass_variant(hot_ctx* c, const hot_slm* slm, int32_t M, const doub
 
 int hot_probe_issue(hot_ctx* c, int kind, int waves_per_simd, int64_t reps, double* out) {
   if (!c) return fail(HOT_EINVAL, "ctx is NULL");
-  if (kind < 0 || kind > 5) return fail(HOT_EINVAL, "probe kind %d outside 0..5", kind);
+  if (kind < 0 || kind > 6) return fail(HOT_EINVAL, "probe kind %d outside 0..6", kind);
   if (waves_per_simd != 1 && waves_per_simd != 2 && waves_per_simd != 4 && waves_per_simd != 8)
     return fail(HOT_EINVAL, "waves per SIMD must be 1, 2, 4 or 8");
   if (reps < 1 || reps > (1LL << 24)) return fail(HOT_EINVAL, "reps = %lld outside 1..2^24", (long long)reps);

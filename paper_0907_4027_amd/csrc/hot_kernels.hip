@@ -23,6 +23,7 @@
 #include "hot_internal.h"
 
 #include <algorithm>
+#include <type_traits>
 
 namespace hot {
 
@@ -1121,17 +1122,25 @@ k_sep(const TrapCoef* __restrict__ coef, const HoloDesc* __restrict__ hd, const 
     return make_float2(__builtin_amdgcn_cosf(t), __builtin_amdgcn_sinf(t));
   };
   const int xg = wave % W, xsub = wave / W;  // the column group this wave fills, and its share of it
-  auto tables_x = [&](int k0, int n) {
+  // (the wave's first column within its group is a compile-time constant in each branch, so the
+  // entries' offsets i and i^2 fold into the code)
+  auto tables_x_from = [&](auto first, int k0, int n) {
+    constexpr int F = decltype(first)::value;
     const double Ut = (double)(2 * (cb + 16 * xg + 8) - (nx - 1));
+    float2* row = xt + (16 * xg + F) * XS;
     for (int j = lane; j < n; j += 64) {
       const TrapCoef k = cf[k0 + j];
       const float2 ks = group_ref(k.g, k.a, Ut);
       const float q = (float)(4.0 * k.g);
 #pragma unroll
-      for (int i = 0; i < 16 / KH; ++i) {
-        const int col = 16 * xg + xsub * (16 / KH) + i;
-        xt[col * XS + j] = factor(ks, q, col - 16 * xg - 8);
-      }
+      for (int i = 0; i < 16 / KH; ++i) row[i * XS + j] = factor(ks, q, F + i - 8);
+    }
+  };
+  auto tables_x = [&](int k0, int n) {
+    if (KH == 1 || xsub == 0) {
+      tables_x_from(std::integral_constant<int, 0>{}, k0, n);
+    } else {
+      tables_x_from(std::integral_constant<int, 16 / KH>{}, k0, n);
     }
   };
   auto tables_y = [&](int k0, int n, bool weighted) {

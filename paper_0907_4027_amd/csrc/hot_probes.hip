@@ -37,6 +37,9 @@ __device__ __forceinline__ unsigned long long real_clock() { return __builtin_am
 // KIND 4: V_MFMA_F32_16X16X4_F32, one accumulator: every product depends on the one before (16 per
 //         repetition).
 // KIND 5: V_MFMA_F32_32X32X2_F32, 4 independent accumulators (16 products per repetition).
+// KIND 6: KIND 3's 16 products with 64 independent sin/cos beside them per repetition (512 matrix
+//         cycles against 512 transcendental cycles per SIMD if each wave ran alone): whether the
+//         transcendental pipe runs while the matrix pipe works.
 typedef float probe_f32x4 __attribute__((ext_vector_type(4)));
 typedef float probe_f32x16 __attribute__((ext_vector_type(16)));
 
@@ -76,6 +79,30 @@ k_probe(long long reps, float seed, float* __restrict__ sink, unsigned long long
         for (int i = 0; i < 8; ++i) s[i] = (i & 1) ? __builtin_amdgcn_cosf(s[i]) : __builtin_amdgcn_sinf(s[i]);
       }
     }
+#pragma unroll
+    for (int i = 0; i < 8; ++i) out += s[i];
+  } else if constexpr (KIND == 6) {
+    probe_f32x4 acc[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) acc[i] = probe_f32x4{seed, 0.0f, 0.0f, 0.0f};
+    float s[8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) s[i] = seed * 0.01f + 0.003f * (float)(lane + i);
+    const float a = 1.0e-3f * seed * (float)(lane + 1), bv = 1.0e-3f * seed;
+    for (long long r = 0; r < reps; ++r) {
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) acc[i] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, bv, acc[i], 0, 0, 0);
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+#pragma unroll
+          for (int i = 0; i < 8; ++i) s[i] = (i & 1) ? __builtin_amdgcn_cosf(s[i]) : __builtin_amdgcn_sinf(s[i]);
+        }
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) out += (acc[i][0] + acc[i][1]) + (acc[i][2] + acc[i][3]);
 #pragma unroll
     for (int i = 0; i < 8; ++i) out += s[i];
   } else if constexpr (KIND == 3 || KIND == 4) {
@@ -180,6 +207,7 @@ int probe_ops_per_rep(int kind) {
     case 3:                                  // FLOPs per lane: 2 x 16 x 16 x 4 per product over 64 lanes
     case 4: return kProbeUnroll * 32;
     case 5: return kProbeUnroll * 64;        // 2 x 32 x 32 x 2 per product over 64 lanes
+    case 6: return kProbeUnroll * 32;        // FLOPs of the products (the sin/cos beside them not counted)
     default: return 0;
   }
 }
@@ -193,6 +221,7 @@ hipError_t launch_probe(hipStream_t s, int kind, int blocks, int threads, long l
     case 3: hipLaunchKernelGGL(k_probe<3>, dim3(blocks), dim3(threads), 0, s, reps, seed, sink, stamps); break;
     case 4: hipLaunchKernelGGL(k_probe<4>, dim3(blocks), dim3(threads), 0, s, reps, seed, sink, stamps); break;
     case 5: hipLaunchKernelGGL(k_probe<5>, dim3(blocks), dim3(threads), 0, s, reps, seed, sink, stamps); break;
+    case 6: hipLaunchKernelGGL(k_probe<6>, dim3(blocks), dim3(threads), 0, s, reps, seed, sink, stamps); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
