@@ -576,12 +576,18 @@ k_iter(HoloDesc one, const TrapCoef* __restrict__ coef, const TrapState* __restr
   const int cbeg = sg * seg_w, lseg = min(nx, cbeg + seg_w) - cbeg;
   const int Vb = 2 * (int)(blockIdx.y * ROWS) - (ny - 1);
 
-  // Every read of the block's own trap data is issued here, unconditionally (threads past M read
-  // trap M - 1 and ignore it), so the update waits for one memory round trip.
+  // Every read of the block's own trap data is issued here, so the update waits for one memory
+  // round trip: threads past M in a wave that holds traps read trap M - 1 and ignore it; waves
+  // whose first thread is past M hold no trap and read nothing.
   const int tm = min((int)threadIdx.x, M - 1);
-  const TrapCoef c_first = cf[tm];
-  const TrapState s_first = st_in[off + tm];
-  const float2 v_first = vacc(tm);
+  TrapCoef c_first = {0.0, 0.0, 0.0, 0.0f, 0.0f};
+  TrapState s_first = {0.0f, 0.0f, 0.0f, 0.0f};
+  float2 v_first = make_float2(0.0f, 0.0f);
+  if (__builtin_amdgcn_readfirstlane((int)threadIdx.x & ~63) < M) {
+    c_first = cf[tm];
+    s_first = st_in[off + tm];
+    v_first = vacc(tm);
+  }
   if (lead) {
     for (int i = threadIdx.x; i < kAccRegions * M; i += NB) {
       const int g = i / M;
