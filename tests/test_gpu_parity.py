@@ -368,6 +368,34 @@ def test_runs_are_bitwise_deterministic(hot, variant):
     assert torch.equal(a.phase, b.phase) and torch.equal(a.V, b.V)
 
 
+@pytest.mark.parametrize("variant", ["onthefly", "separable"])
+def test_degenerate_field_is_reported(hot, variant):
+    """<|V|> = 0 (the update is skipped and HOT_EDEGENERATE reported): with every weight zero the
+    first mask is arg 0 = 0 on every pixel, and traps in the focal plane at the pixel grid's own
+    spatial frequencies (a = k/16 revolutions per pixel-index unit: whole periods in every 16
+    columns) then receive exactly nothing.  Each block's trap sums cancel to FP32 rounding, far below
+    the fixed-point unit of the iteration kernels' sums (2^-8 at 2048^2), so V is exactly zero.  The
+    call with statistics reports it; without them hot_sync does, once; the context stays usable."""
+    slm = W.Slm(2048, 2048)
+    lf = slm.wavelength * slm.focal
+    xyz = np.array([[k * 2 * lf / (16 * slm.pitch), 1e-5 * i, 0.0] for i, k in enumerate((1, 2, 3, 5))])
+    th = np.zeros(4)
+    w0 = torch.zeros(4, device="cuda")
+    with hot.Context(0) as c:
+        c.set_variant(variant)
+        with pytest.raises(hot.HotError) as e:
+            c.hot_gsw(slm, xyz, th, 3, w0=w0)
+        assert e.value.code == hot.HOT_EDEGENERATE
+        c.hot_gsw(slm, xyz, th, 3, w0=w0, stats=False)
+        with pytest.raises(hot.HotError) as e:
+            c.hot_sync()
+        assert e.value.code == hot.HOT_EDEGENERATE
+        c.hot_sync()  # the flag was cleared
+        r = c.hot_gsw(slm, xyz, th, 3)  # unit weights: the mask sends light to every trap
+        torch.cuda.synchronize()
+        assert np.all(np.abs(as_complex(to_np(r.V))) > 0.1)
+
+
 def test_seeded_theta_matches_splitmix(ctx):
     p = W.random_problem(360, 128, 96, 12)
     g = ctx.hot_rs(p.slm, p.xyz, None, seed=987654321)
