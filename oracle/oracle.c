@@ -28,6 +28,9 @@
  * grating Fourier coefficient, FFT special case, backward/forward duality,
  * GS/GSW ascent, mirror and conjugation symmetry, translation covariance,
  * brute force on tiny grids, finite-difference gradient.
+ * Parity unpinned: the update's degenerate branches (<|V|> = 0: update skipped,
+ * ORC_EDEGENERATE; |V_m| below 1e-12 <|V|>: that floor, theta_m kept), which no
+ * FP64 workload reaches.
  */
 #include <math.h>
 #include <stdint.h>
