@@ -1172,13 +1172,14 @@ k_sep(const TrapCoef* __restrict__ coef, const HoloDesc* __restrict__ hd, const 
   // the update's inputs arrive, and only then does the GS/GSW update.
   const VAcc vacc{acc_in, T, off, unscale};
   const bool lead = blockIdx.x == 0 && blockIdx.y == 0;
-  // unconditional loads (threads past M read trap M - 1; their copies are never used as trap
-  // threadIdx.x), so the values stay in registers
+  // the coefficients are loaded unconditionally (threads past M read trap M - 1; their copies are
+  // never used as trap threadIdx.x), so the values stay in registers
   const int tm = min((int)threadIdx.x, M - 1);
   const TrapCoef c_first = coef[off + tm];
   float2 v_first = make_float2(0.0f, 0.0f);
   TrapState s_first = {0.0f, 0.0f, 0.0f, 0.0f};
-  if (kPixel && MODE != 3) {
+  // the state and V only in waves that hold traps (waves whose first thread is past M never use them)
+  if (kPixel && MODE != 3 && __builtin_amdgcn_readfirstlane((int)threadIdx.x & ~63) < M) {
     s_first = st_in[off + tm];
     if (MODE == 0 && upd != 0) v_first = vacc(tm);
   }
