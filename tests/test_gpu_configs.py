@@ -5,6 +5,7 @@
 * 8 x 512^2 x 64 traps, Eq. 1 and its adjoint in one batched call each, and through the
   autograd Function with the trap-intensity loss, against the oracle per hologram; uneven trap
   counts on a ragged grid; the Adam loop against an FP64 Adam driven by the oracle's gradient.
+* The stored-matrix variant at the benchmarked sizes (512^2 x 100 and 1024^2 x 256).
 * Identical-input checks of single passes: the oracle is handed the GPU's own weights and trap
   phases (pixel pass, Eq. 3) or the GPU's own phase mask (trap pass, Eq. 1) after every iteration,
   so the comparison measures one pass of FP32 arithmetic, not the GSW map's amplification of it.
@@ -255,3 +256,16 @@ def test_1024sq_256_traps_final_passes(vctx):
     p = W.c3()
     idx = np.random.default_rng(8).choice(p.slm.n, 65536, replace=False)
     per_pass_check(vctx, p, [p.iters], idx=idx)
+
+
+@pytest.mark.parametrize("name", ["c2", "c3"])
+def test_stored_variant_at_benchmark_sizes(hot, name):
+    """The stored-matrix variant in the configurations the benchmark times it in: 512^2 x 100 after
+    50 iterations (a 210 MB matrix) and 1024^2 x 256 after 40 (2.15 GB): the final pixel pass (in
+    full, or on 65536 sampled pixels at 1024^2) and the final trap pass, on identical inputs, at
+    the parity bar."""
+    p = getattr(W, name)()
+    idx = None if name == "c2" else np.random.default_rng(9).choice(p.slm.n, 65536, replace=False)
+    with hot.Context(0) as c:
+        c.set_variant("stored")
+        per_pass_check(c, p, [p.iters], idx=idx)
