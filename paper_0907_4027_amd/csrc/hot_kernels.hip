@@ -173,15 +173,23 @@ struct VAcc {
   const unsigned long long* __restrict__ acc;
   int T, off;
   float unscale;
-  __device__ float2 operator()(int k) const {
-    unsigned long long w8[kAccRegions];
+  // the eight words of trap k (loads only: nothing waits for them here) ...
+  __device__ void load(int k, unsigned long long (&w8)[kAccRegions]) const {
 #pragma unroll
     for (int r = 0; r < kAccRegions; ++r) w8[r] = acc[(size_t)r * T + off + k];
-    // a tree of adds (exact, so the order is free): three dependent steps instead of seven
+  }
+  // ... and V from them: a tree of adds (exact, so the order is free), three dependent steps
+  // instead of seven
+  __device__ float2 sum(const unsigned long long (&w8)[kAccRegions]) const {
     const unsigned long long w = ((w8[0] + w8[1]) + (w8[2] + w8[3])) + ((w8[4] + w8[5]) + (w8[6] + w8[7]));
     const int re = (int)(unsigned)w;
     const int im = (int)((unsigned)(w >> 32) - (unsigned)(re >> 31));
     return make_float2((float)re * unscale, (float)im * unscale);
+  }
+  __device__ float2 operator()(int k) const {
+    unsigned long long w8[kAccRegions];
+    load(k, w8);
+    return sum(w8);
   }
 };
 
@@ -507,22 +515,43 @@ __device__ __forceinline__ void trap_pass_block(const float4* rec, int rp, const
 }
 
 // Stage the records and K of trap m for the block's spans of a row segment starting at column
-// cbeg with lseg pixels, for its ROWS rows (row coordinate of row hr: Vb + 2 hr).
+// cbeg with lseg pixels, for its ROWS rows (row coordinate of row hr: Vb + 2 hr).  First the span
+// references of the trap, a' per span and K per (row, span) pair (geometry only: they do not depend
+// on the iteration's state) ...
 template <int HS, int ROWS>
-__device__ __forceinline__ void stage_spans(float4* rec, int rp, float* kt, int mp, int m, const TrapCoef& c, int nx,
-                                            int cbeg, int lseg, int Vb, float theta_rev, float w) {
+struct SpanRefs {
+  float ap[HS], k[ROWS * HS];
+};
+template <int HS, int ROWS>
+__device__ __forceinline__ SpanRefs<HS, ROWS> span_refs(const TrapCoef& c, int nx, int cbeg, int lseg, int Vb) {
+  SpanRefs<HS, ROWS> r;
 #pragma unroll
   for (int h = 0; h < HS; ++h) {
     const int cc = centre_col(cbeg + kSpan * h, min(max(lseg - kSpan * h, 1), kSpan));
     const double Uc = (double)(2 * cc - (nx - 1));
-    const float ap = block_slope(c, Uc);
+    r.ap[h] = block_slope(c, Uc);
+#pragma unroll
+    for (int hr = 0; hr < ROWS; ++hr) r.k[hr * HS + h] = block_const(c, Uc, (double)(Vb + 2 * hr));
+  }
+  return r;
+}
+// ... and its records and K from them, with the state's theta and w.
+template <int HS, int ROWS>
+__device__ __forceinline__ void stage_refs(float4* rec, int rp, float* kt, int mp, int m, const SpanRefs<HS, ROWS>& r,
+                                           float gf, float theta_rev, float w) {
+#pragma unroll
+  for (int h = 0; h < HS; ++h) {
 #pragma unroll
     for (int hr = 0; hr < ROWS; ++hr) {
-      const float k = block_const(c, Uc, (double)(Vb + 2 * hr));
-      stage_record(rec + (hr * HS + h) * rp, m, ap, c.gf, k, theta_rev, w);
-      kt[(hr * HS + h) * mp + m] = k;
+      stage_record(rec + (hr * HS + h) * rp, m, r.ap[h], gf, r.k[hr * HS + h], theta_rev, w);
+      kt[(hr * HS + h) * mp + m] = r.k[hr * HS + h];
     }
   }
+}
+template <int HS, int ROWS>
+__device__ __forceinline__ void stage_spans(float4* rec, int rp, float* kt, int mp, int m, const TrapCoef& c, int nx,
+                                            int cbeg, int lseg, int Vb, float theta_rev, float w) {
+  stage_refs<HS, ROWS>(rec, rp, kt, mp, m, span_refs<HS, ROWS>(c, nx, cbeg, lseg, Vb), c.gf, theta_rev, w);
 }
 
 // ------------------------------------------------------------------ fused iteration kernel
@@ -578,15 +607,22 @@ k_iter(HoloDesc one, const TrapCoef* __restrict__ coef, const TrapState* __restr
 
   // Every read of the block's own trap data is issued here, so the update waits for one memory
   // round trip: threads past M in a wave that holds traps read trap M - 1 and ignore it; waves
-  // whose first thread is past M hold no trap and read nothing.
+  // whose first thread is past M hold no trap and read nothing.  The coefficients go first: they
+  // stay in the L2 from launch to launch and return about a thousand cycles before the
+  // accumulators (rewritten by the previous launch, so read from beyond the L2), and loads return
+  // in order, so the trap's span references (FP64) are formed while the accumulators are in flight.
   const int tm = min((int)threadIdx.x, M - 1);
   TrapCoef c_first = {0.0, 0.0, 0.0, 0.0f, 0.0f};
   TrapState s_first = {0.0f, 0.0f, 0.0f, 0.0f};
   float2 v_first = make_float2(0.0f, 0.0f);
+  SpanRefs<HS, ROWS> r_first = {};
   if (__builtin_amdgcn_readfirstlane((int)threadIdx.x & ~63) < M) {
     c_first = cf[tm];
+    asm volatile("" ::: "memory");  // (keeps the loads below after this one)
     s_first = st_in[off + tm];
     v_first = vacc(tm);
+    r_first = span_refs<HS, ROWS>(c_first, nx, cbeg, lseg, Vb);
+    __builtin_amdgcn_sched_barrier(0);  // all of it before the first use of the accumulators
   }
   if (lead) {
     for (int i = threadIdx.x; i < kAccRegions * M; i += NB) {
@@ -596,7 +632,11 @@ k_iter(HoloDesc one, const TrapCoef* __restrict__ coef, const TrapState* __restr
   }
   auto coef_of = [&](int m) { return m == (int)threadIdx.x ? c_first : cf[m]; };
   auto stage = [&](int m, const TrapCoef& c, const TrapState& s) {
-    stage_spans<HS, ROWS>(refs, rp, kts, mp, m, c, nx, cbeg, lseg, Vb, s.theta_rev, s.w);
+    if (m == (int)threadIdx.x) {
+      stage_refs<HS, ROWS>(refs, rp, kts, mp, m, r_first, c.gf, s.theta_rev, s.w);
+    } else {
+      stage_spans<HS, ROWS>(refs, rp, kts, mp, m, c, nx, cbeg, lseg, Vb, s.theta_rev, s.w);
+    }
   };
   if (upd == 0) {
     for (int m = threadIdx.x; m < M; m += NB) stage(m, coef_of(m), m == (int)threadIdx.x ? s_first : st_in[off + m]);
@@ -1176,12 +1216,17 @@ k_sep(const TrapCoef* __restrict__ coef, const HoloDesc* __restrict__ hd, const 
   // never used as trap threadIdx.x), so the values stay in registers
   const int tm = min((int)threadIdx.x, M - 1);
   const TrapCoef c_first = coef[off + tm];
-  float2 v_first = make_float2(0.0f, 0.0f);
+  if ((int)threadIdx.x < Mp) cf[threadIdx.x] = (int)threadIdx.x < M ? c_first : TrapCoef{0.0, 0.0, 0.0, 0.0f, 0.0f};
+  __builtin_amdgcn_sched_barrier(0);
+  // The state and V's words are read once the coefficients are in (those stay in the L2 from
+  // launch to launch and return about a thousand cycles before the accumulators, which the
+  // previous launch rewrote), so the first X table is built while these are in flight; V is
+  // summed only where the update needs it.
   TrapState s_first = {0.0f, 0.0f, 0.0f, 0.0f};
-  // the state and V only in waves that hold traps (waves whose first thread is past M never use them)
-  if (kPixel && MODE != 3 && __builtin_amdgcn_readfirstlane((int)threadIdx.x & ~63) < M) {
+  unsigned long long w_first[kAccRegions] = {};
+  if (kPixel && MODE != 3) {
     s_first = st_in[off + tm];
-    if (MODE == 0 && upd != 0) v_first = vacc(tm);
+    if (MODE == 0) vacc.load(tm, w_first);  // (acc_in is valid even when upd == 0)
   }
   if (MODE == 0 && lead) {
     for (int i = threadIdx.x; i < kAccRegions * M; i += NT) {
@@ -1190,7 +1235,6 @@ k_sep(const TrapCoef* __restrict__ coef, const HoloDesc* __restrict__ hd, const 
     }
   }
   for (int m = NT + (int)threadIdx.x; m < Mp; m += NT) cf[m] = m < M ? coef[off + m] : TrapCoef{0.0, 0.0, 0.0, 0.0f, 0.0f};
-  if ((int)threadIdx.x < Mp) cf[threadIdx.x] = (int)threadIdx.x < M ? c_first : TrapCoef{0.0, 0.0, 0.0, 0.0f, 0.0f};
   __syncthreads();
   if constexpr (kPixel) {
     tables_x(0, min(sc, Mp));
@@ -1203,6 +1247,9 @@ k_sep(const TrapCoef* __restrict__ coef, const HoloDesc* __restrict__ hd, const 
         if (lead) st_out[off + m] = st;
         cw[m] = trap_weight(st);
       };
+#pragma unroll
+      for (int r = 0; r < kAccRegions; ++r) asm volatile("" : "+v"(w_first[r]));  // (the sum stays here)
+      const float2 v_first = vacc.sum(w_first);
       update_traps<NT, VAcc, decltype(emit), true>(vacc, st_in, off, M, upd, sh,
                                                    lead ? stats + 3 * ((size_t)b * stat_stride + kstat) : nullptr,
                                                    lead ? flag : nullptr, emit, v_first, s_first);
