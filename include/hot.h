@@ -107,7 +107,8 @@ int hot_set_variant(hot_ctx* ctx, int variant);
 enum hot_tuning_key {
   HOT_TUNE_PIXELS_PER_LANE = 1, /* fused iteration kernel: pixels per lane, 1 or 2 */
   HOT_TUNE_TRAPS_PER_LANE = 2,  /* trap pass: traps each lane accumulates: 1..6 or 8 */
-  HOT_TUNE_SEGMENT = 3,         /* trap pass: pixels of a row per block, 64..1024 */
+  HOT_TUNE_SEGMENT = 3,         /* pixels of a row per block, 64..1024, for the fused iteration kernel
+                                   and the stand-alone trap pass (built-in: 512 and 256 pixels) */
   HOT_TUNE_SLICES = 4,          /* trap pass: at most this many pixel slices per wave, 1..16 */
   HOT_TUNE_GRAPHS = 5,          /* 1 (default): replay a captured hipGraph of a solve's launch
                                    sequence when shapes and buffers repeat; 0: launch eagerly */
