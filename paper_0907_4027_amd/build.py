@@ -21,8 +21,8 @@ OUT = os.path.join(HERE, "libhot.so")
 OBJDIR = os.path.join(HERE, "_build")
 # packed FP32 (v_pk_*_f32) code generation stays off; the host pass warns that it does
 # not know the feature, which is harmless
-# kernel arguments: the first 16 SGPRs' worth are preloaded at wave launch (no scalar load
-# to wait for before the first memory reads of a kernel)
+# kernel arguments: leading scalar and pointer arguments (up to 14 SGPRs) are preloaded at wave
+# launch (a kernel whose argument list starts with an aggregate loads them with scalar loads)
 FLAGS = ["-O3", "--offload-arch=gfx950", "-std=c++17", "-fPIC",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-mllvm", "-amdgpu-kernarg-preload-count=16",

@@ -513,6 +513,8 @@ SepArgs sep_args(hot_ctx* c, const Plan& P, int mode, float* phase, int K) {
   a.mmax = P.mmax;
   a.sc = P.sep_sc;
   a.kh = mode == 0 ? P.sep_kh : 1;
+  a.one_m = P.one.m;
+  a.one_off = P.one.off;
   a.coef = (const TrapCoef*)c->coef.p;
   a.hd = (const HoloDesc*)c->hd.p;
   a.stats = (float*)c->stats.p;

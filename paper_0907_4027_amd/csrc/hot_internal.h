@@ -166,6 +166,7 @@ struct SepArgs {
   int W = 4;     // tiles per block: a block covers 16 rows x 16 W columns
   int kh = 1;    // mode 0: waves per tile (1, or 2 taking half of the traps each)
   int B = 1, nx = 0, ny = 0, mmax = 0;
+  int one_m = 0, one_off = 0;  // B == 1: the hologram's trap count and offset, passed by value
   int sc = 16;   // traps per LDS super-chunk (multiple of 16); sep_lds_bytes(W, sc, mmax, kh) <= kSepLdsMax
   const TrapCoef* coef = nullptr;
   const HoloDesc* hd = nullptr;
