@@ -69,6 +69,7 @@ struct hot_ctx {
   int tune_q = 0, tune_tpl = 0, tune_seg = 0, tune_amax = 0, tune_sepw = 0, tune_sepc = 0, tune_rows = 0;
   int tune_sepk = 0;
   int tune_fract = 0;
+  int num_cu = 256;  // compute units of the device (launch-shape choices)
   int use_graphs = 1;
   // captured launch sequences of solve(), keyed by everything they bake in (shapes, pointers)
   struct GraphEntry {
@@ -301,7 +302,16 @@ int prepare_into(hot_ctx* c, const hot_slm* slm, int B, const int32_t* counts, c
   {
     const int q = c->tune_q == 2 ? 2 : 1;
     int segmax = 512 * q;
-    if (c->tune_seg > 0) segmax = std::min(segmax, c->tune_seg);
+    if (c->tune_seg > 0) {
+      segmax = std::min(segmax, c->tune_seg);
+    } else if (c->tune_q == 0 && (int64_t)row_segments(slm->nx, slm->ny, 512).nseg * slm->ny * B < 4 * c->num_cu) {
+      // 256-pixel segments when 512-pixel ones would leave fewer than four blocks per compute
+      // unit: the blocks sharing a unit finish one after another (the oldest wave's instructions
+      // issue first), and the last one's trap pass then runs alone on its SIMDs, for half as long
+      // with half-length segments (GSW 512^2 x 100: 16.7 against 17.1 us per iteration in situ;
+      // at 1024^2 x 256, eight blocks per unit, 512-pixel segments stay 0.2 % faster)
+      segmax = 256;
+    }
     P.fg = row_segments(slm->nx, slm->ny, segmax);
     // two pixels per lane once a segment outgrows 256 pixels (measured faster than one pixel on
     // 512-thread blocks: the pixel pass reuses each trap record twice)
@@ -775,6 +785,11 @@ int hot_create(hot_ctx** out, int device, void* stream) {
     return code;
   };
   if (hipSetDevice(device) != hipSuccess) return bail(fail(HOT_EDEVICE, "hipSetDevice(%d) failed", device));
+  {
+    int ncu = 0;
+    if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess && ncu > 0)
+      c->num_cu = ncu;
+  }
   if (hipStreamCreateWithFlags(&c->own_stream, hipStreamNonBlocking) != hipSuccess)
     return bail(fail(HOT_EDEVICE, "stream creation failed"));
   c->stream = (hipStream_t)stream;

@@ -210,6 +210,14 @@ __device__ void update_traps(VGet vmem, const TrapState* __restrict__ st_in, int
     if (PRE && k == (int)threadIdx.x) return vpre;
     return vmem(k);
   };
+  // PRE: the modulus of the thread's own V, its reciprocal and arg V do not need <|V|>; they are
+  // formed here, so that their latency overlaps the block-wide sum instead of following it
+  float own_amp = 0.0f, own_rcp = 0.0f, own_th = 0.0f;
+  if (PRE && mode != 0 && (int)threadIdx.x < M) {
+    own_amp = __builtin_amdgcn_sqrtf(vpre.x * vpre.x + vpre.y * vpre.y);
+    own_rcp = __builtin_amdgcn_rcpf(own_amp);
+    own_th = phase_of(vpre.y, vpre.x);
+  }
   float sa = 0.0f, si = 0.0f, mx = -1.0f, mn = 3.0e38f;
   for (int k = threadIdx.x; k < M; k += NT) {
     const float2 v = getv(k);
@@ -249,14 +257,21 @@ __device__ void update_traps(VGet vmem, const TrapState* __restrict__ st_in, int
   for (int k = threadIdx.x; k < M; k += NT) {
     TrapState s = (PRE && k == (int)threadIdx.x) ? spre : st_in[off + k];
     if (mode != 0 && !degenerate) {
-      const float2 v = getv(k);
-      const float vr = v.x, vi = v.y;
-      const float amp = __builtin_amdgcn_sqrtf(vr * vr + vi * vi);
+      float amp, rcp_amp, th;  // |V_m|, its reciprocal, arg V_m in [0, 2pi]
+      if (PRE && k == (int)threadIdx.x) {
+        amp = own_amp;
+        rcp_amp = own_rcp;
+        th = own_th;
+      } else {
+        const float2 v = getv(k);
+        amp = __builtin_amdgcn_sqrtf(v.x * v.x + v.y * v.y);
+        rcp_amp = __builtin_amdgcn_rcpf(amp);
+        th = phase_of(v.y, v.x);
+      }
       const bool tiny = amp < floor_abs;
-      if (mode == 2) s.w *= mean_abs * __builtin_amdgcn_rcpf(tiny ? floor_abs : amp);
+      if (mode == 2) s.w *= mean_abs * (tiny ? __builtin_amdgcn_rcpf(floor_abs) : rcp_amp);
       if (!tiny) {
-        const float th = phase_of(vi, vr);  // arg V in [0, 2pi], kept in (-pi, pi]
-        s.theta_rad = th > 3.14159265358979324f ? th - kTwoPi : th;
+        s.theta_rad = th > 3.14159265358979324f ? th - kTwoPi : th;  // kept in (-pi, pi]
         s.theta_rev = s.theta_rad * kInv2Pi;
       }
     }
@@ -641,6 +656,7 @@ k_iter(HoloDesc one, const TrapCoef* __restrict__ coef, const TrapState* __restr
       stage_spans<HS, ROWS>(refs, rp, kts, mp, m, c, nx, cbeg, lseg, Vb, s.theta_rev, s.w);
     }
   };
+  for (int hs = 0; hs < ROWS * HS; ++hs) pad_records<NB>(refs + hs * rp, M);  // (no trap's record)
   if (upd == 0) {
     for (int m = threadIdx.x; m < M; m += NB) stage(m, coef_of(m), m == (int)threadIdx.x ? s_first : st_in[off + m]);
   } else {
@@ -652,7 +668,6 @@ k_iter(HoloDesc one, const TrapCoef* __restrict__ coef, const TrapState* __restr
                                                  lead ? stats + 3 * ((size_t)b * stat_stride + kstat) : nullptr,
                                                  lead ? flag : nullptr, emit, v_first, s_first);
   }
-  for (int hs = 0; hs < ROWS * HS; ++hs) pad_records<NB>(refs + hs * rp, M);
   __syncthreads();
 
   // pixel pass: pixel q of the lane is pixel i = Q tid + q of the segment (adjacent pixels, so the
