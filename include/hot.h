@@ -108,9 +108,10 @@ enum hot_tuning_key {
   HOT_TUNE_PIXELS_PER_LANE = 1, /* fused iteration kernel: pixels per lane, 1 or 2 */
   HOT_TUNE_TRAPS_PER_LANE = 2,  /* trap pass: traps each lane accumulates: 1..6 or 8 */
   HOT_TUNE_SEGMENT = 3,         /* pixels of a row per block, 64..1024, for the fused iteration kernel
-                                   and the stand-alone trap pass (built-in: 512 pixels for the fused
-                                   kernel, 256 when 512-pixel segments would give its grid fewer
-                                   than four blocks per compute unit; 256 for the trap pass) */
+                                   and the stand-alone trap pass (built-in: 256 pixels for the fused
+                                   kernel on holograms of 64 traps or more, one at a time or in a
+                                   batch whose 512-pixel grid would give fewer than four blocks per
+                                   compute unit, else 512; 256 for the trap pass) */
   HOT_TUNE_SLICES = 4,          /* trap pass: at most this many pixel slices per wave, 1..16 */
   HOT_TUNE_GRAPHS = 5,          /* 1 (default): replay a captured hipGraph of a solve's launch
                                    sequence when shapes and buffers repeat; 0: launch eagerly */

@@ -304,12 +304,16 @@ int prepare_into(hot_ctx* c, const hot_slm* slm, int B, const int32_t* counts, c
     int segmax = 512 * q;
     if (c->tune_seg > 0) {
       segmax = std::min(segmax, c->tune_seg);
-    } else if (c->tune_q == 0 && (int64_t)row_segments(slm->nx, slm->ny, 512).nseg * slm->ny * B < 4 * c->num_cu) {
-      // 256-pixel segments when 512-pixel ones would leave fewer than four blocks per compute
-      // unit: the blocks sharing a unit finish one after another (the oldest wave's instructions
-      // issue first), and the last one's trap pass then runs alone on its SIMDs, for half as long
-      // with half-length segments (GSW 512^2 x 100: 16.7 against 17.1 us per iteration in situ;
-      // at 1024^2 x 256, eight blocks per unit, 512-pixel segments stay 0.2 % faster)
+    } else if (c->tune_q == 0 && P.mmax >= 64 &&
+               (B == 1 || (int64_t)row_segments(slm->nx, slm->ny, 512).nseg * slm->ny * B < 4 * c->num_cu)) {
+      // 256-pixel segments for a hologram of 64 traps or more (or a batch whose 512-pixel grid
+      // would leave fewer than four blocks per compute unit): the blocks sharing a unit finish
+      // close together, and twice the blocks shorten the last one's trap pass.  Measured per
+      // iteration in situ, 256 against 512 pixels: 512^2 x 100 15.4 against 16.5 us, 1024^2 x 256
+      // 110.1 against 111.2 us, 768^2 x 81 25.0 against 29.6 us; with fewer traps the update and
+      // the trap sums, repeated by every block, cost more than the tail saves (768^2 x 9 19.8
+      // against 15.0 us, 1024 x 768 x 8 13.5 against 10.5 us), and a batch of 16 holograms of
+      // 4..256 traps at 512^2 runs 2 % faster on 512-pixel segments
       segmax = 256;
     }
     P.fg = row_segments(slm->nx, slm->ny, segmax);

@@ -629,6 +629,13 @@ k_iter(HoloDesc one, const TrapCoef* __restrict__ coef, const TrapState* __restr
   // stay in the L2 from launch to launch and return about a thousand cycles before the
   // accumulators (rewritten by the previous launch, so read from beyond the L2), and loads return
   // in order, so the trap's span references (FP64) are formed while the accumulators are in flight.
+  // Wave priority: the update and the pixel pass run at priority 1, the trap pass at 0.  The
+  // blocks sharing a compute unit otherwise finish in age order (the oldest wave's instructions
+  // issue first), and the youngest block's trap pass is left to run alone, one wave per SIMD, at
+  // the end of the launch; with the trap passes yielding to the pixel passes, the younger blocks
+  // catch up while the older ones take their trap passes, and the unit's blocks reach the trap
+  // pass, and the end, closer together.
+  __builtin_amdgcn_s_setprio(1);
   const int tm = min((int)threadIdx.x, M - 1);
   TrapCoef c_first = {0.0, 0.0, 0.0, 0.0f, 0.0f};
   TrapState s_first = {0.0f, 0.0f, 0.0f, 0.0f};
@@ -707,6 +714,7 @@ k_iter(HoloDesc one, const TrapCoef* __restrict__ coef, const TrapState* __restr
   auto add_sum = [&](int m, float2 v) {
     __hip_atomic_fetch_add(mine + m, pack_sum(v, scale), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   };
+  __builtin_amdgcn_s_setprio(0);
   trap_pass_block<W, HS, TPL, FRACT, ROWS>(refs, rp, kts, mp, M, G, A, px, len, red, add_sum);
 }
 
@@ -1240,6 +1248,9 @@ k_sep(const TrapCoef* __restrict__ coef, const TrapState* __restrict__ st_in,
   // the coefficients are loaded unconditionally (threads past M read trap M - 1; their copies are
   // never used as trap threadIdx.x), so the values stay in registers
   const int tm = min((int)threadIdx.x, M - 1);
+  // wave priority: the update, the tables and the pixel pass at 1, the trap pass at 0, so that the
+  // blocks sharing a compute unit reach the trap pass, and the end, closer together (as in k_iter)
+  __builtin_amdgcn_s_setprio(1);
   const TrapCoef c_first = coef[off + tm];
   if ((int)threadIdx.x < Mp) cf[threadIdx.x] = (int)threadIdx.x < M ? c_first : TrapCoef{0.0, 0.0, 0.0, 0.0f, 0.0f};
   __builtin_amdgcn_sched_barrier(0);
@@ -1379,6 +1390,7 @@ k_sep(const TrapCoef* __restrict__ coef, const TrapState* __restrict__ st_in,
     }
   }
 
+  __builtin_amdgcn_s_setprio(0);
   if constexpr (kTrap) {
     // per tile of 16 traps: T^T[r][m] = sum_c E[r][c] conj X[m][c], then sum_r conj Y[m][r] T^T[r][m]
     const int nblk = gridDim.x * gridDim.y, blk = blockIdx.y * gridDim.x + blockIdx.x;
