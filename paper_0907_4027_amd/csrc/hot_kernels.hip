@@ -32,12 +32,12 @@ namespace {
 constexpr float kInv2Pi = 0.159154943091895336f;  // FP32(1 / (2 pi))
 constexpr float kTwoPi = 6.28318530717958648f;    // FP32(2 pi)
 
-// The XCD (accelerator complex die) the wave runs on: hardware register XCC_ID, bits 3:0.
 // Holograms of at least this many traps run the iteration kernels' update and pixel pass at a
 // higher wave priority than their trap pass (measured: 768^2 x 49 traps 21.9 -> 20.2 us per
 // iteration, 512^2 x 100 16.6 -> 15.2 us; 768^2 x 25 14.6 -> 15.5 us, 1024 x 768 x 8 7.4 -> 9.7 us).
 constexpr int kPriorityTraps = 40;
 
+// The XCD (accelerator complex die) the wave runs on: hardware register XCC_ID, bits 3:0.
 __device__ __forceinline__ int xcc_id() { return __builtin_amdgcn_s_getreg(20 | (0 << 6) | ((4 - 1) << 11)) & 15; }
 
 template <bool FRACT>
@@ -634,6 +634,7 @@ k_iter(HoloDesc one, const TrapCoef* __restrict__ coef, const TrapState* __restr
   // stay in the L2 from launch to launch and return about a thousand cycles before the
   // accumulators (rewritten by the previous launch, so read from beyond the L2), and loads return
   // in order, so the trap's span references (FP64) are formed while the accumulators are in flight.
+  //
   // Wave priority (holograms of kPriorityTraps traps or more): the update and the pixel pass run
   // at priority 1, the trap pass at 0.  The blocks sharing a compute unit otherwise finish in age
   // order (the oldest wave's instructions issue first), and the youngest block's trap pass is left
